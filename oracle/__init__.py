@@ -1,0 +1,159 @@
+"""FP64 CPU oracle (test infrastructure only).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never loads it and
+shares no code with it.
+
+Thin ctypes wrapper around ``oracle/liborc.so`` (built from ``orc.c`` by
+``oracle.build.build()``).  All arrays are numpy complex128 in the host
+layouts ``U[T,L1,L2,L3,4,3,3]``, ``psi[T,L1,L2,L3,4,3]`` and
+``C[T,L1,L2,L3,12,12]``.  ``alpha`` is a table of T positive numbers in the
+convention ``S' = alpha S`` (the reciprocal of the function the paper
+factorises in eq. redeft).
+
+The pins that make this oracle trustworthy live in ``tests/test_oracle_*.py``
+(closed-form free propagator, dense LU, similarity, gamma5-hermiticity, gauge
+covariance, an analytic clover field).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+ORC_OK, ORC_EINVAL, ORC_ENOMEM, ORC_ENOCONV, ORC_EBREAK = 0, -1, -2, -3, -4
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liborc.so")
+        if not os.path.exists(path):
+            from .build import build
+            build()
+        lib = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        lib.orc_clover.argtypes = [ip, dp, ctypes.c_double, dp]
+        lib.orc_apply.argtypes = [ip, ctypes.c_int, dp, dp, ctypes.c_double, dp, ctypes.c_int, dp, dp]
+        lib.orc_apply_modified.argtypes = [ip, ctypes.c_int, dp, dp, ctypes.c_double, dp,
+                                           ctypes.c_double, ctypes.c_double, dp, dp]
+        lib.orc_solve.argtypes = [ip, ctypes.c_int, dp, dp, ctypes.c_double, dp, ctypes.c_int, dp,
+                                  ctypes.c_double, ctypes.c_int, dp, dp, dp]
+        lib.orc_cpp.argtypes = [ip, ctypes.c_int, dp, ctypes.c_int, dp]
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_get_threads.restype = ctypes.c_int
+        lib.orc_gamma.argtypes = [ctypes.c_int, dp]
+        _LIB = lib
+    return _LIB
+
+
+def _dims(dims):
+    return (ctypes.c_int * 4)(*[int(d) for d in dims])
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _check(rc, what):
+    if rc != ORC_OK:
+        raise OracleError(f"{what} failed with code {rc}")
+
+
+def set_threads(n):
+    _lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(_lib().orc_get_threads())
+
+
+def gamma(mu):
+    out = np.zeros((4, 4), dtype=np.complex128)
+    _lib().orc_gamma(int(mu), _ptr(out))
+    return out
+
+
+def clover(U, csw):
+    """Dense 12x12 clover term c_sw (i/4) sum sigma F per site."""
+    U = _c128(U)
+    dims = U.shape[:4]
+    C = np.zeros(tuple(dims) + (12, 12), dtype=np.complex128)
+    _check(_lib().orc_clover(_dims(dims), _ptr(U), float(csw), _ptr(C)), "orc_clover")
+    return C
+
+
+def apply(U, C, M, psi, alpha=None, bc_t=-1, dagger=False):
+    """alpha (D+M) alpha^-1 psi (or its adjoint); alpha None means no preconditioning."""
+    U = _c128(U)
+    psi = _c128(psi)
+    dims = U.shape[:4]
+    out = np.zeros_like(psi)
+    a = None if alpha is None else np.ascontiguousarray(alpha, dtype=np.float64)
+    Cc = None if C is None else _c128(C)
+    _check(_lib().orc_apply(_dims(dims), int(bc_t), _ptr(U), _ptr(Cc), float(M), _ptr(a),
+                            int(bool(dagger)), _ptr(psi), _ptr(out)), "orc_apply")
+    return out
+
+
+def apply_modified(U, C, M, psi, alpha, alpha_T=1.0, alpha_m1=1.0, bc_t=-1):
+    """D'+M through the paper's modified time derivatives and boundary rule."""
+    U = _c128(U)
+    psi = _c128(psi)
+    dims = U.shape[:4]
+    out = np.zeros_like(psi)
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    Cc = None if C is None else _c128(C)
+    _check(_lib().orc_apply_modified(_dims(dims), int(bc_t), _ptr(U), _ptr(Cc), float(M), _ptr(a),
+                                     float(alpha_T), float(alpha_m1), _ptr(psi), _ptr(out)),
+           "orc_apply_modified")
+    return out
+
+
+def solve(U, C, M, eta, alpha=None, r=1e-13, solver="bicgstab", maxit=100000, bc_t=-1,
+          return_prec=False, allow_unconverged=False):
+    """Solve (D+M) S = eta via the alpha-preconditioned system.
+
+    Returns ``(S, info)`` (or ``(S, S', info)``) with info = dict(iters,
+    relres_prec, relres).
+    """
+    U = _c128(U)
+    eta = _c128(eta)
+    dims = U.shape[:4]
+    S = np.zeros_like(eta)
+    Sp = np.zeros_like(eta) if return_prec else None
+    info = np.zeros(3)
+    a = None if alpha is None else np.ascontiguousarray(alpha, dtype=np.float64)
+    Cc = None if C is None else _c128(C)
+    sid = {"bicgstab": 0, "cgnr": 1}[solver]
+    rc = _lib().orc_solve(_dims(dims), int(bc_t), _ptr(U), _ptr(Cc), float(M), _ptr(a), sid,
+                          _ptr(eta), float(r), int(maxit), _ptr(S), _ptr(Sp), _ptr(info))
+    if rc != ORC_OK and not (allow_unconverged and rc == ORC_ENOCONV):
+        raise OracleError(f"orc_solve failed with code {rc} after {int(info[0])} iterations")
+    d = dict(iters=int(info[0]), relres_prec=float(info[1]), relres=float(info[2]), code=rc)
+    return (S, Sp, d) if return_prec else (S, d)
+
+
+def cpp(S, x0_src=0):
+    """C_PP(t) = -sum_x sum_cols |S|^2 per timeslice, t = (x0 - x0_src) mod T.
+    S: ([ncols,] T, L1, L2, L3, 4, 3)."""
+    S = _c128(S)
+    if S.ndim == 6:
+        S = S[None]
+    dims = S.shape[1:5]
+    out = np.zeros(dims[0])
+    _check(_lib().orc_cpp(_dims(dims), S.shape[0], _ptr(S), int(x0_src), _ptr(out)), "orc_cpp")
+    return out
