@@ -1,0 +1,162 @@
+/*
+ * libdp — distance-preconditioned Wilson-clover inversion on one MI355X (gfx950).
+ *
+ * Method: G.M. de Divitiis, R. Petronzio, N. Tantalo, "Distance
+ * preconditioning for lattice Dirac operators".  The lattice Dirac system
+ * (D[U] + M) S = eta (eq. linsysunprec) is solved through the redefined
+ * fields of eq. redeft and the preconditioned system of eq. linsysprec,
+ * whose operator differs from D + M only in the time-direction derivatives
+ * (modified nabla_0, nabla*_0 and the boundary rule eq. redeftbc), and the
+ * propagator and correlator are restored afterwards (eq. backcorrection).
+ *
+ * Conventions of this interface
+ * -----------------------------
+ *  - dims = {T, L1, L2, L3}: time first; every extent even and >= 2.
+ *  - Host field layouts are complex128 interleaved (re, im) with x0 slowest
+ *    and x3 fastest:
+ *      gauge  U  [x0][x1][x2][x3][mu][a][b]   mu = 0 (time), 1, 2, 3
+ *      spinor    [x0][x1][x2][x3][spin][colour]  (12 complex per site)
+ *      clover C  [x0][x1][x2][x3][12][12]     row/col 3*spin + colour
+ *    Several right-hand sides are stored one after the other.
+ *  - The operator is D + M with D the O(a)-improved Wilson operator
+ *      D = 1/2 sum_mu {gamma_mu (nabla_mu + nabla*_mu) - nabla*_mu nabla_mu}
+ *          + c_sw (i/4) sum_{mu,nu} sigma_mu_nu Fhat_mu_nu
+ *    in the chiral basis (gamma5 = diag(1,1,-1,-1)), Fhat the clover-leaf
+ *    field strength; fermions periodic in space, time boundary bc_t.
+ *  - alpha is a table of T positive numbers used as S' = alpha(x0) S,
+ *    eta' = alpha(x0) eta, so S = S'/alpha and C_PP = C'_PP / alpha^2.  This
+ *    is the reciprocal of the function the paper factorises in eq. redeft.
+ *  - The stopping rule (eq. stopping) is read as
+ *      |eta' - (D'+M) S'|_2 <= r |eta'|_2   per right-hand side,
+ *    checked on an FP64 recomputation of the residual.
+ *
+ * Ownership and errors
+ * --------------------
+ *  - Every function returns DP_OK (0) or a negative DP_ERR_* code and never
+ *    throws; dp_last_error() gives a message for the last failure on a ctx.
+ *  - Host buffers passed in are read (or written) before the call returns;
+ *    the caller keeps ownership.  Device pointers (the *_dev variants) must be
+ *    device memory of the ctx's GPU in the same host layout; the library
+ *    enqueues its work on the given HIP stream (NULL: the ctx's own stream)
+ *    and returns when the results are complete.
+ *  - A ctx owns all device memory it allocates (gauge field, clover blocks,
+ *    per-mass inverses, solver work space) until dp_destroy.
+ *  - One host thread at a time per ctx.
+ */
+#ifndef DP_H
+#define DP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define DP_OK 0
+#define DP_ERR_INVALID_ARG (-1)
+#define DP_ERR_OOM (-2)
+#define DP_ERR_DEVICE (-3)
+#define DP_ERR_NOT_CONVERGED (-4)
+#define DP_ERR_BREAKDOWN (-5)
+#define DP_ERR_NONFINITE (-6)
+#define DP_ERR_BAD_STATE (-7)
+
+/* inner precision of a solve */
+#define DP_PREC_F64 0 /* FP64 throughout */
+#define DP_PREC_F32 1 /* FP32 storage and arithmetic inside, FP64 outside */
+#define DP_PREC_F16 2 /* FP16 storage with per-site scales, FP32 arithmetic inside */
+
+/* Krylov solver */
+#define DP_SOLVER_BICGSTAB 0 /* van der Vorst 1992 */
+#define DP_SOLVER_CGNR 1     /* CG on the normal equations of the Schur operator */
+
+/* dp_apply flags */
+#define DP_PRECOND 1     /* apply D' + M = alpha (D+M) alpha^-1 (else D + M) */
+#define DP_DAGGER 2      /* apply the adjoint */
+#define DP_HOP_ONLY 4    /* apply only the hopping term (no 4 + M, no clover) */
+#define DP_APPLY_SCHUR 8 /* even-site Schur operator A_ee - H_eo A_oo^-1 H_oe on the
+                            even part of the input; the odd part of the output is 0 */
+#define DP_APPLY_F32 16  /* compute in the FP32 kernels (input rounded to FP32) */
+#define DP_APPLY_F16 32  /* compute in the FP16-storage kernels */
+
+typedef struct dp_ctx dp_ctx;
+
+typedef struct {
+  double r;        /* target relative residual of the preconditioned system (> 0) */
+  int solver;      /* DP_SOLVER_* */
+  int precision;   /* DP_PREC_* (inner precision) */
+  int max_iter;    /* cap on Krylov iterations per right-hand side (> 0) */
+  double delta;    /* inner relative residual reduction per outer step (0: default
+                      1e-5 for F32, 5e-3 for F16; ignored for F64) */
+  int x0_src;      /* source timeslice: C_PP is indexed by t = (x0 - x0_src) mod T */
+  int ncols_group; /* columns summed into one C_PP (e.g. 12 for a point source);
+                      0 means every right-hand side gets its own C_PP */
+} dp_params;
+
+typedef struct {
+  int status;        /* DP_OK, DP_ERR_NOT_CONVERGED, DP_ERR_NONFINITE ... */
+  int iters;         /* Krylov iterations (BiCGStab steps or CG steps) */
+  int outer;         /* FP64 residual recomputations (outer steps) */
+  int hop_calls;     /* applications of the hop kernel (each one a parity) */
+  int restarts;      /* BiCGStab breakdown restarts */
+  double true_res;   /* FP64 |eta' - D'S'| / |eta'| of the returned solution */
+  double seconds;    /* wall time of the solve (shared by a batch) */
+} dp_info;
+
+/* Create a context on GPU `device` for a lattice dims = {T, L1, L2, L3}
+ * (all even, >= 2), time boundary bc_t = -1 (antiperiodic) or +1 (periodic).
+ * The state starts with unit links, c_sw = 0, M = 0 and alpha = 1. */
+int dp_create(const int dims[4], int bc_t, int device, dp_ctx** out);
+void dp_destroy(dp_ctx* ctx);
+const char* dp_last_error(const dp_ctx* ctx);
+
+/* Gauge links, host layout above (T*L1*L2*L3*4*9 complex).  Resets the clover
+ * term to c_sw = 0 and drops cached per-mass inverses. */
+int dp_set_gauge(dp_ctx* ctx, const double* U);
+/* Same from device memory of the ctx's GPU. */
+int dp_set_gauge_dev(dp_ctx* ctx, const void* U_dev, void* hip_stream);
+
+/* Clover term c_sw (i/4) sum sigma F from the resident links (built on the GPU). */
+int dp_set_clover(dp_ctx* ctx, double csw);
+/* A caller-supplied clover field, host layout [site][12][12]; it must be
+ * Hermitian and commute with gamma5 (block diagonal in the two chiralities),
+ * else DP_ERR_INVALID_ARG. */
+int dp_set_clover_field(dp_ctx* ctx, const double* C);
+
+/* Bare mass M (operator D + M), or kappa with M = 1/(2 kappa) - 4. */
+int dp_set_mass(dp_ctx* ctx, double M);
+int dp_set_kappa(dp_ctx* ctx, double kappa);
+
+/* Distance profile alpha(x0), T entries, each finite and > 0. */
+int dp_set_alpha(dp_ctx* ctx, const double* alpha);
+
+/* out = op(in) for one full-lattice spinor (host layout).  flags:
+ * DP_PRECOND (alpha-preconditioned operator), DP_DAGGER (adjoint),
+ * DP_HOP_ONLY (hopping term only) or DP_APPLY_SCHUR (even-odd Schur
+ * operator), and DP_APPLY_F32 / DP_APPLY_F16 to run the inner-precision
+ * kernels (for checking them; the result is returned in FP64).  The
+ * operator uses the ctx's current gauge field, clover term, mass and alpha. */
+int dp_apply(dp_ctx* ctx, const double* in, double* out, int flags);
+
+/* Solve (D+M) S = eta for nrhs right-hand sides (host layout, nrhs spinors)
+ * through the preconditioned system, to the residue p->r.
+ *   S    : nullable; receives the nrhs restored solutions (host layout)
+ *   cpp  : nullable; receives C_PP(t) = -sum_x tr[S^+ S], T doubles per group
+ *          of p->ncols_group right-hand sides (or per right-hand side)
+ *   info : nullable; nrhs entries
+ * Returns DP_OK when every right-hand side met r, DP_ERR_NOT_CONVERGED when
+ * one hit max_iter (S, cpp and info are still filled), or another error. */
+int dp_solve(dp_ctx* ctx, const double* eta, int nrhs, const dp_params* p, double* S, double* cpp,
+             dp_info* info);
+/* Same with eta and S in device memory (host layout); cpp and info on the host. */
+int dp_solve_dev(dp_ctx* ctx, const void* eta_dev, int nrhs, const dp_params* p, void* S_dev, double* cpp,
+                 dp_info* info, void* hip_stream);
+
+/* Device bytes a context would hold for the gauge field and clover of a
+ * lattice, plus the solver work space for nrhs right-hand sides at the given
+ * precision, plus one per-mass inverse per new mass. */
+long long dp_footprint_bytes(const int dims[4], int nrhs, int precision, int new_masses);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DP_H */

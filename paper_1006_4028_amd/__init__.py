@@ -1,0 +1,152 @@
+"""Python binding of libdp (distance-preconditioned Wilson-clover inversion on
+MI355X).  Argument marshalling only: every step of the computation runs in
+the HIP kernels of ``libdp.so``.  Host arrays are numpy complex128 in the
+layouts of ``include/dp.h``; device arrays are torch CUDA (HIP) tensors of
+complex128 (or float64 with a trailing 2) in the same layout.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import DPError  # noqa: F401
+
+__all__ = ["Lattice", "DPError", "footprint_bytes"]
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def footprint_bytes(dims, nrhs, precision="f64", new_masses=1):
+    d = (ctypes.c_int * 4)(*dims)
+    return int(L.lib().dp_footprint_bytes(d, int(nrhs), L.DP_PREC[precision], int(new_masses)))
+
+
+class Lattice:
+    """One lattice with a resident gauge field on one GPU (a dp_ctx)."""
+
+    def __init__(self, dims, bc_t=-1, device=0):
+        self.dims = tuple(int(d) for d in dims)
+        self.T = self.dims[0]
+        self.V = int(np.prod(self.dims))
+        self._L = L.lib()
+        h = ctypes.c_void_p()
+        rc = self._L.dp_create((ctypes.c_int * 4)(*self.dims), int(bc_t), int(device), ctypes.byref(h))
+        if rc != L.DP_OK:
+            raise DPError(rc, "dp_create failed")
+        self._h = h
+
+    # ------------------------------------------------------------ plumbing
+    def _check(self, rc, allow=()):
+        if rc != L.DP_OK and rc not in allow:
+            raise DPError(rc, self._L.dp_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.dp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------ state
+    def set_gauge(self, U):
+        if hasattr(U, "is_cuda") and U.is_cuda:
+            import torch
+            stream = torch.cuda.current_stream(U.device).cuda_stream
+            self._check(self._L.dp_set_gauge_dev(self._h, ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(stream)))
+            return
+        U = _c128(U)
+        assert U.size == self.V * 36, "gauge field must have T*L1*L2*L3*4*9 entries"
+        self._check(self._L.dp_set_gauge(self._h, _ptr(U)))
+
+    def set_clover(self, csw):
+        self._check(self._L.dp_set_clover(self._h, float(csw)))
+
+    def set_clover_field(self, C):
+        C = _c128(C)
+        assert C.size == self.V * 144
+        self._check(self._L.dp_set_clover_field(self._h, _ptr(C)))
+
+    def set_mass(self, M):
+        self._check(self._L.dp_set_mass(self._h, float(M)))
+
+    def set_kappa(self, kappa):
+        self._check(self._L.dp_set_kappa(self._h, float(kappa)))
+
+    def set_alpha(self, alpha):
+        a = np.ascontiguousarray(alpha, dtype=np.float64)
+        assert a.shape == (self.T,)
+        self._check(self._L.dp_set_alpha(self._h, _ptr(a)))
+
+    # ------------------------------------------------------------ operator
+    def apply(self, psi, precond=False, dagger=False, hop_only=False, schur=False, precision="f64"):
+        psi = _c128(psi)
+        assert psi.size == self.V * 12
+        out = np.zeros_like(psi)
+        flags = (L.DP_PRECOND if precond else 0) | (L.DP_DAGGER if dagger else 0)
+        flags |= (L.DP_HOP_ONLY if hop_only else 0) | (L.DP_APPLY_SCHUR if schur else 0)
+        flags |= {"f64": 0, "f32": L.DP_APPLY_F32, "f16": L.DP_APPLY_F16}[precision]
+        self._check(self._L.dp_apply(self._h, _ptr(psi), _ptr(out), flags))
+        return out
+
+    # ------------------------------------------------------------ solves
+    @staticmethod
+    def _params(r, solver, precision, max_iter, delta, x0_src, ncols_group):
+        return L.dp_params(float(r), L.DP_SOLVER[solver], L.DP_PREC[precision], int(max_iter), float(delta),
+                           int(x0_src), int(ncols_group))
+
+    @staticmethod
+    def _infos(info):
+        return [dict(status=i.status, iters=i.iters, outer=i.outer, hop_calls=i.hop_calls,
+                     restarts=i.restarts, true_res=i.true_res, seconds=i.seconds) for i in info]
+
+    def solve(self, eta, r=1e-11, solver="bicgstab", precision="f64", max_iter=10000, delta=0.0, x0_src=0,
+              ncols_group=0, want_S=True, allow_unconverged=False):
+        """Solve (D+M) S = eta for eta of shape ([nrhs,] T, L1, L2, L3, 4, 3).
+        Returns (S, cpp, info)."""
+        eta = _c128(eta)
+        if eta.ndim == 6:
+            eta = eta[None]
+        n = eta.shape[0]
+        S = np.zeros_like(eta) if want_S else None
+        grp = ncols_group if ncols_group > 0 else 1
+        cpp = np.zeros((n // grp, self.T))
+        info = (L.dp_info * n)()
+        p = self._params(r, solver, precision, max_iter, delta, x0_src, ncols_group)
+        rc = self._L.dp_solve(self._h, _ptr(eta), n, ctypes.byref(p), _ptr(S) if want_S else None, _ptr(cpp),
+                              info)
+        self._check(rc, allow=(L.DP_ERR_NOT_CONVERGED,) if allow_unconverged else ())
+        return S, cpp, self._infos(info)
+
+    def solve_dev(self, eta_t, S_t=None, r=1e-11, solver="bicgstab", precision="f64", max_iter=10000, delta=0.0,
+                  x0_src=0, ncols_group=0, allow_unconverged=False):
+        """Device variant: eta_t (and S_t) are torch CUDA tensors in host layout."""
+        import torch
+        assert eta_t.is_cuda and eta_t.is_contiguous()
+        n = eta_t.numel() * eta_t.element_size() // (self.V * 12 * 16)
+        grp = ncols_group if ncols_group > 0 else 1
+        cpp = np.zeros((n // grp, self.T))
+        info = (L.dp_info * n)()
+        p = self._params(r, solver, precision, max_iter, delta, x0_src, ncols_group)
+        stream = torch.cuda.current_stream(eta_t.device).cuda_stream
+        rc = self._L.dp_solve_dev(self._h, ctypes.c_void_p(eta_t.data_ptr()), n, ctypes.byref(p),
+                                  ctypes.c_void_p(S_t.data_ptr()) if S_t is not None else None, _ptr(cpp), info,
+                                  ctypes.c_void_p(stream))
+        self._check(rc, allow=(L.DP_ERR_NOT_CONVERGED,) if allow_unconverged else ())
+        return cpp, self._infos(info)

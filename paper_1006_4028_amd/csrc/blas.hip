@@ -1,0 +1,186 @@
+// Fused vector kernels of the Krylov solvers (BiCGStab of van der Vorst 1992
+// and CG on the normal equations) over the even sites of every active slot,
+// with their global reductions fused in (see block_reduce_finalize).  The
+// arithmetic is FP64 whatever the storage precision; scalars come from the
+// slot's device-resident SlotScalars.
+#include "dp_device.h"
+
+namespace dp {
+
+namespace {
+
+using z = cx<double>;
+
+template <int P>
+__device__ __forceinline__ void ld(const SpinorRef& f, int slot, int i, int Vh, z (&s)[12]) {
+  SpinorIO<P>::load(f, slot, i, Vh, s);
+}
+template <int P>
+__device__ __forceinline__ void st(const SpinorRef& f, int slot, int i, int Vh, const z (&s)[12]) {
+  SpinorIO<P>::store(f, slot, i, Vh, s);
+}
+
+__device__ __forceinline__ double norm2(const z (&a)[12]) {
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) s += a[c].x * a[c].x + a[c].y * a[c].y;
+  return s;
+}
+
+template <int P, int OP>
+__global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
+  constexpr int PX = P == F16 ? F32 : P;
+  const Geom& g = a.g;
+  const int slot = blockIdx.y;
+  if (a.mask && !a.mask[slot]) return;  // uniform over the slot's blocks
+  const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int Vh = g.Vh;
+  double red[4] = {0.0, 0.0, 0.0, 0.0};
+  int nv = 0;
+  if constexpr (OP == OP_BICG_INIT || OP == OP_CG_XR || OP == OP_SUB64 || OP == OP_NORM) nv = 1;
+  if constexpr (OP == OP_BICG_XR) nv = 3;
+  if (i < Vh) {
+    z A[12], B[12], C[12];
+    if constexpr (OP == OP_ZERO) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) A[c] = z{0.0, 0.0};
+      st<P>(a.v[0], slot, i, Vh, A);
+    } else if constexpr (OP == OP_COPY) {
+      ld<P>(a.v[1], slot, i, Vh, A);
+      st<P>(a.v[0], slot, i, Vh, A);
+    } else if constexpr (OP == OP_BICG_INIT) {
+      ld<P>(a.v[1], slot, i, Vh, A);
+      st<P>(a.v[0], slot, i, Vh, A);
+      red[0] = norm2(A);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) B[c] = z{0.0, 0.0};
+      st<P>(a.v[2], slot, i, Vh, B);
+      st<P>(a.v[3], slot, i, Vh, B);
+      st<PX>(a.v[4], slot, i, Vh, B);
+    } else if constexpr (OP == OP_BICG_P) {
+      const SlotScalars& s = a.sc[slot];
+      const z beta{s.beta[0], s.beta[1]}, omega{s.omega[0], s.omega[1]};
+      ld<P>(a.v[0], slot, i, Vh, A);  // p
+      ld<P>(a.v[1], slot, i, Vh, B);  // r
+      ld<P>(a.v[2], slot, i, Vh, C);  // v
+#pragma unroll
+      for (int c = 0; c < 12; ++c) A[c] = B[c] + cmul(beta, A[c] - cmul(omega, C[c]));
+      st<P>(a.v[0], slot, i, Vh, A);
+    } else if constexpr (OP == OP_BICG_S) {
+      const SlotScalars& s = a.sc[slot];
+      const z alpha{s.alpha[0], s.alpha[1]};
+      ld<P>(a.v[1], slot, i, Vh, B);  // r
+      ld<P>(a.v[2], slot, i, Vh, C);  // v
+#pragma unroll
+      for (int c = 0; c < 12; ++c) A[c] = B[c] - cmul(alpha, C[c]);
+      st<P>(a.v[0], slot, i, Vh, A);
+    } else if constexpr (OP == OP_BICG_XR) {
+      const SlotScalars& s = a.sc[slot];
+      const z alpha{s.alpha[0], s.alpha[1]}, omega{s.omega[0], s.omega[1]};
+      ld<PX>(a.v[0], slot, i, Vh, A);  // x
+      ld<P>(a.v[1], slot, i, Vh, B);   // p
+      ld<P>(a.v[2], slot, i, Vh, C);   // s
+#pragma unroll
+      for (int c = 0; c < 12; ++c) A[c] = A[c] + cmul(alpha, B[c]) + cmul(omega, C[c]);
+      st<PX>(a.v[0], slot, i, Vh, A);
+      ld<P>(a.v[4], slot, i, Vh, B);  // t
+#pragma unroll
+      for (int c = 0; c < 12; ++c) C[c] = C[c] - cmul(omega, B[c]);  // r
+      st<P>(a.v[3], slot, i, Vh, C);
+      ld<P>(a.v[5], slot, i, Vh, B);  // rh
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const z d = cjmul(B[c], C[c]);
+        red[0] += d.x;
+        red[1] += d.y;
+      }
+      red[2] = norm2(C);
+    } else if constexpr (OP == OP_CG_XR) {
+      const double ca = a.sc[slot].cg_a;
+      ld<PX>(a.v[0], slot, i, Vh, A);  // x
+      ld<P>(a.v[1], slot, i, Vh, B);   // p
+#pragma unroll
+      for (int c = 0; c < 12; ++c) A[c] = A[c] + ca * B[c];
+      st<PX>(a.v[0], slot, i, Vh, A);
+      ld<P>(a.v[2], slot, i, Vh, B);  // r
+      ld<P>(a.v[3], slot, i, Vh, C);  // w
+#pragma unroll
+      for (int c = 0; c < 12; ++c) B[c] = B[c] - ca * C[c];
+      st<P>(a.v[2], slot, i, Vh, B);
+      red[0] = norm2(B);
+    } else if constexpr (OP == OP_CG_P) {
+      const double cb = a.sc[slot].cg_b;
+      ld<P>(a.v[0], slot, i, Vh, A);  // p
+      ld<P>(a.v[1], slot, i, Vh, B);  // z
+#pragma unroll
+      for (int c = 0; c < 12; ++c) A[c] = B[c] + cb * A[c];
+      st<P>(a.v[0], slot, i, Vh, A);
+    } else if constexpr (OP == OP_SCALE_COPY) {
+      const double f = a.slot_scale[slot];
+      ld<F64>(a.v[1], slot, i, Vh, B);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) A[c] = f * B[c];
+      st<P>(a.v[0], slot, i, Vh, A);
+    } else if constexpr (OP == OP_AXPY_SCALED) {
+      const double f = a.slot_scale[slot];
+      ld<F64>(a.v[0], slot, i, Vh, A);
+      ld<PX>(a.v[1], slot, i, Vh, B);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) A[c] = A[c] + f * B[c];
+      st<F64>(a.v[0], slot, i, Vh, A);
+    } else if constexpr (OP == OP_SUB64) {
+      ld<F64>(a.v[1], slot, i, Vh, B);
+      ld<F64>(a.v[2], slot, i, Vh, C);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) A[c] = B[c] - C[c];
+      st<F64>(a.v[0], slot, i, Vh, A);
+      red[0] = norm2(A);
+    } else if constexpr (OP == OP_TO64) {
+      ld<P>(a.v[1], slot, i, Vh, B);
+      st<F64>(a.v[0], slot, i, Vh, B);
+    } else if constexpr (OP == OP_NORM) {
+      ld<P>(a.v[1], slot, i, Vh, B);
+      red[0] = norm2(B);
+    }
+  }
+  if (nv > 0 && a.red.fin != FIN_NONE) block_reduce_finalize(a.red, nv, red, slot, blockIdx.x, gridDim.x);
+}
+
+template <int P>
+hipError_t launch_p(int op, const BlasArgs& a, dim3 grid, hipStream_t st) {
+  switch (op) {
+#define DP_BLAS_CASE(OPV) \
+  case OPV: hipLaunchKernelGGL((blas_kernel<P, OPV>), grid, dim3(kBlock), 0, st, a); break;
+    DP_BLAS_CASE(OP_ZERO)
+    DP_BLAS_CASE(OP_COPY)
+    DP_BLAS_CASE(OP_BICG_INIT)
+    DP_BLAS_CASE(OP_BICG_P)
+    DP_BLAS_CASE(OP_BICG_S)
+    DP_BLAS_CASE(OP_BICG_XR)
+    DP_BLAS_CASE(OP_CG_XR)
+    DP_BLAS_CASE(OP_CG_P)
+    DP_BLAS_CASE(OP_SCALE_COPY)
+    DP_BLAS_CASE(OP_AXPY_SCALED)
+    DP_BLAS_CASE(OP_SUB64)
+    DP_BLAS_CASE(OP_NORM)
+    DP_BLAS_CASE(OP_TO64)
+#undef DP_BLAS_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_blas(int op, const BlasArgs& a, hipStream_t st) {
+  if (a.nslots <= 0 || a.g.Vh <= 0) return hipErrorInvalidValue;
+  const dim3 grid(reduction_blocks(a.g), a.nslots);
+  switch (a.prec) {
+    case F64: return launch_p<F64>(op, a, grid, st);
+    case F32: return launch_p<F32>(op, a, grid, st);
+    case F16: return launch_p<F16>(op, a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dp

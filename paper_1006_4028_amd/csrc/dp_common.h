@@ -1,0 +1,217 @@
+// Internal declarations shared by the HIP translation units of libdp.
+//
+// Device data layout (all fields split by checkerboard parity p = (x0+x1+x2+x3)&1,
+// index within a parity i = lexicographic_site >> 1 with x0 slowest, so a
+// timeslice is a contiguous range of Vsh = L1*L2*L3/2 indices):
+//
+//   spinor, FP64 : double2 [12][Vh]        component c = 3*spin + colour
+//   spinor, FP32 : float4  [6][Vh]         components (2k, 2k+1) packed
+//   spinor, FP16 : uint4   [3][Vh]         8 halves (4 complex) per uint4,
+//                  + float scale[Vh]       value = half * scale (per-site max)
+//   links, FP64  : double2 [4][9][Vh]      U_mu(x)[a][b] at the sites of one parity
+//   links, FP32  : float2  [4][9][Vh]
+//   links, FP16  : __half2 [4][9][Vh]      |U_ab| <= 1 for SU(3), no scale
+//   clover, FP64 : double2 [36][Vh]        two Hermitian 6x6 blocks (upper and
+//   clover, FP32 : float4  [18][Vh]        lower chirality), 36 reals each:
+//   clover, FP16 : uint4   [9][Vh]         6 diagonal reals, then the 15 upper
+//                  + float scale[Vh]       off-diagonal entries (i<j, row-major)
+//
+// Several right-hand sides ("slots") are stored one after the other with a
+// fixed slot stride.
+#pragma once
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace dp {
+
+enum Prec { F64 = 0, F32 = 1, F16 = 2 };
+
+struct Geom {
+  int T, L1, L2, L3;
+  int L3h;  // L3 / 2
+  int Vsh;  // sites of one parity in one timeslice
+  int Vh;   // sites of one parity
+};
+
+// Bytes of one site of one parity in each storage format.
+inline size_t spinor_site_bytes(int prec) { return prec == F64 ? 192 : prec == F32 ? 96 : 48; }
+inline size_t spinor_scale_bytes(int prec) { return prec == F16 ? 4 : 0; }
+inline size_t link_site_bytes(int prec) { return prec == F64 ? 576 : prec == F32 ? 288 : 144; }
+inline size_t clover_site_bytes(int prec) { return prec == F64 ? 576 : prec == F32 ? 288 : 144; }
+
+// A spinor field of one parity for nslots right-hand sides.
+struct SpinorRef {
+  void* data = nullptr;     // storage units as documented above
+  float* scale = nullptr;   // FP16 only
+  long slot_stride = 0;     // elements of the storage unit between slots
+  long scale_stride = 0;    // floats between slots
+  int prec = F64;
+};
+
+// A clover-block field of one parity (C or A^-1).
+struct CloverRef {
+  const void* data = nullptr;
+  const float* scale = nullptr;
+  int prec = F64;
+};
+
+// Per-slot parameters in device memory.
+struct SlotTable {
+  const double* ratio = nullptr;  // [nslots][4][T]: fwd, bwd, fwd_dag, bwd_dag
+  const double* m4 = nullptr;     // [nslots] 4 + M
+  const int* mask = nullptr;      // [nslots] nonzero = slot takes part
+  const void* const* ainv = nullptr;          // [nslots] A_oo^-1 field of the slot's mass
+  const float* const* ainv_scale = nullptr;   // [nslots] FP16 scales (or null)
+};
+
+// Solver scalars of one slot, device resident (written by the finalisers of
+// fused reductions, read by the following kernels of the same iteration).
+struct SlotScalars {
+  double rho[2], alpha[2], omega[2], beta[2];  // BiCGStab, complex
+  double rr;      // |r|^2 of the iterated residual
+  double rh2;     // |rh|^2 of the shadow residual
+  double zz;      // CGNR |z|^2
+  double cg_a;    // CGNR step length
+  double cg_b;    // CGNR beta
+  int breakdown;  // 1: rho collapsed, 2: <rh, v> = 0, 3: omega = 0
+  int pad;
+};
+
+// Epilogues of the hop kernel.
+enum Epi {
+  EPI_HOP = 0,      // out = H in
+  EPI_INV = 1,      // out = A^-1 (H in)               (slot mass)
+  EPI_DIAG = 2,     // out = (C + m4) xin + sign * H in
+  EPI_SUB = 3,      // out = xin - H in
+  EPI_INV_SUB = 4,  // out = A^-1 (xin - H in)
+};
+
+// Reductions fused into a kernel's epilogue; results land in per-slot partials
+// and the last block of each slot folds them in a fixed order and runs a finaliser.
+enum Red {
+  RED_NONE = 0,
+  RED_DOT_EXT = 1,  // <w, out>      (w = extra vector, e.g. the shadow residual)
+  RED_TS = 2,       // <out, xin>, |out|^2
+  RED_NORM = 3,     // |out|^2
+};
+
+enum Fin {
+  FIN_NONE = 0,
+  FIN_BICG_ALPHA = 1,  // sums <rh, v>            -> alpha = rho / <rh, v>
+  FIN_BICG_OMEGA = 2,  // sums <t, s>, |t|^2      -> omega
+  FIN_BICG_RHO = 3,    // sums <rh, r>, |r|^2     -> rho, beta, rr, breakdown
+  FIN_BICG_INIT = 4,   // sums |r|^2 (rh = r)     -> rho, rr, rh2, alpha = omega = 1
+  FIN_CG_ALPHA = 5,    // sums |w|^2              -> cg_a = zz / |w|^2
+  FIN_CG_BETA = 6,     // sums |z|^2              -> cg_b = |z|^2 / zz, zz
+  FIN_CG_INIT = 7,     // sums |z|^2              -> zz
+  FIN_RR = 8,          // sums |r|^2              -> rr
+  FIN_STORE = 9,       // raw sums                -> out_sums[slot][k]
+};
+
+struct ReduceRef {
+  int red = RED_NONE;
+  int fin = FIN_NONE;
+  SpinorRef w;               // RED_DOT_EXT partner
+  double* partials = nullptr;   // [nslots][nblocks][4]
+  unsigned* counters = nullptr; // [nslots], zero between launches
+  SlotScalars* sc = nullptr;    // [nslots]
+  double* out_sums = nullptr;   // FIN_STORE: [nslots][4]
+};
+
+struct HopArgs {
+  Geom g;
+  int p;               // parity of the output sites
+  int dag;             // 1: adjoint hop (projectors flipped, reciprocal ratios)
+  int epi;
+  double sign;         // EPI_DIAG sign of the hop term
+  const void* U_out;   // links at output-parity sites
+  const void* U_in;    // links at input-parity sites
+  int link_prec;
+  SpinorRef in, out, xin;
+  CloverRef clov;      // C of the output parity (EPI_DIAG)
+  SlotTable slots;
+  ReduceRef red;
+  int nslots;
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `stream` and return hipSuccess or the launch error.
+
+hipError_t launch_hop(const HopArgs& a, hipStream_t stream);
+
+// FP64 host-layout gauge field [site][mu][3][3] (device copy) -> SoA parity fields;
+// U_aos == nullptr gives unit links
+hipError_t launch_gauge_reorder(const Geom& g, const double2* U_aos, void* U_eo[2], int prec,
+                                hipStream_t stream);
+// Clover blocks from the FP64 parity links: out_eo[p] = packed C (FP64), both parities.
+hipError_t launch_clover_build(const Geom& g, const double2* U64_eo[2], double csw, double2* C_eo[2],
+                               hipStream_t stream);
+// Host-layout dense clover [site][12][12] (device copy) -> packed blocks; flags
+// nonzero on entries outside the two chiral blocks or non-Hermitian parts.
+hipError_t launch_clover_pack(const Geom& g, const double2* C_aos, double2* C_eo[2], int* bad,
+                              hipStream_t stream);
+// A^-1 = (C + m4)^-1 per block (FP64 Gauss-Jordan with pivoting), packed; *bad is
+// set when a block is singular.
+hipError_t launch_clover_invert(const Geom& g, const double2* C64, double m4, double2* Ainv64, int* bad,
+                                hipStream_t stream);
+// out = A^-1 in per slot (the slot's A^-1 field), FP64 parity fields.
+hipError_t launch_clover_apply(const Geom& g, const SlotTable& slots, SpinorRef in, SpinorRef out, int nslots,
+                               hipStream_t stream);
+// Convert packed FP64 clover blocks to FP32 / FP16(+scale).
+hipError_t launch_clover_convert(const Geom& g, const double2* C64, void* out, float* scale, int prec,
+                                 hipStream_t stream);
+
+// Host-layout spinors [slot][site][4][3] complex128 (device) <-> parity fields.
+// alpha_mul: optional [nslots][T] factors applied on the way (nullptr = 1).
+hipError_t launch_spinor_import(const Geom& g, const double2* aos, int nslots, long aos_slot_stride,
+                                int p, SpinorRef dst, const double* alpha_mul, hipStream_t stream);
+hipError_t launch_spinor_export(const Geom& g, SpinorRef even, SpinorRef odd, int nslots,
+                                const double* alpha_div, double2* aos, long aos_slot_stride,
+                                hipStream_t stream);
+// Per-timeslice sum of |psi|^2 over both parities, written to cpp[slot][t]
+// (as -sum, t = (x0 - x0_src[slot]) mod T), FP64 fields, divided by alpha^2.
+hipError_t launch_cpp(const Geom& g, SpinorRef even, SpinorRef odd, int nslots, const double* alpha,
+                      const int* x0_src, double* cpp, hipStream_t stream);
+
+// ------------------------------------------------------------- BLAS kernels
+// Vector kernels over the even sites of every active slot.  Krylov vectors
+// are in the inner precision P; the inner solution x is FP32 when P is FP16
+// (P otherwise); FP64 vectors are named as such.
+struct BlasArgs {
+  Geom g;
+  int nslots;
+  int prec;                    // inner precision P
+  const int* mask = nullptr;   // [nslots]
+  SlotScalars* sc = nullptr;   // [nslots]
+  const double* slot_scale = nullptr;  // [nslots] per-slot factor (scale ops)
+  SpinorRef v[6];
+  ReduceRef red;
+};
+
+enum BlasOp {
+  OP_ZERO = 0,        // v0 = 0
+  OP_COPY = 1,        // v0 = v1                                  (P)
+  OP_BICG_INIT = 2,   // v0(rh) = v1(r); v2(p) = 0; v3(v) = 0; v4(x) = 0;  red |r|^2 -> FIN_BICG_INIT
+  OP_BICG_P = 3,      // v0(p) = v1(r) + beta (p - omega v2(v))
+  OP_BICG_S = 4,      // v0(s) = v1(r) - alpha v2(v)
+  OP_BICG_XR = 5,     // v0(x) += alpha v1(p) + omega v2(s); v3(r) = s - omega v4(t); red <v5(rh), r>, |r|^2
+  OP_CG_XR = 6,       // v0(x) += a v1(p); v2(r) -= a v3(w);      red |r|^2
+  OP_CG_P = 7,        // v0(p) = v1(z) + b p
+  OP_SCALE_COPY = 8,  // v0(P) = slot_scale * v1(F64)
+  OP_AXPY_SCALED = 9, // v0(F64) += slot_scale * v1(x precision)
+  OP_SUB64 = 10,      // v0(F64) = v1(F64) - v2(F64);             red |v0|^2
+  OP_NORM = 11,       // red |v1|^2                               (precision of v1)
+  OP_TO64 = 12,       // v0(F64) = v1(P)
+};
+
+hipError_t launch_blas(int op, const BlasArgs& a, hipStream_t stream);
+
+// Number of blocks a reduction launch uses for a given geometry (so that the
+// caller can size the partials buffer).
+int reduction_blocks(const Geom& g);
+constexpr int kBlock = 256;
+
+}  // namespace dp

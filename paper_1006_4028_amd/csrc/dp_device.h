@@ -1,0 +1,454 @@
+// Device-side helpers: complex arithmetic, field loads/stores per storage
+// format, geometry, and the fused block reduction with its finalisers.
+#pragma once
+#include "dp_common.h"
+
+namespace dp {
+
+template <typename R>
+struct cx {
+  R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> mk(R a, R b) { return cx<R>{a, b}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.x, s * a.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+// conj(a) * b
+template <typename R>
+__device__ __forceinline__ cx<R> cjmul(cx<R> a, cx<R> b) { return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x}; }
+// i * a
+template <typename R>
+__device__ __forceinline__ cx<R> ti(cx<R> a) { return {-a.y, a.x}; }
+// a += b * c
+template <typename R>
+__device__ __forceinline__ void cfma(cx<R>& a, cx<R> b, cx<R> c) {
+  a.x += b.x * c.x - b.y * c.y;
+  a.y += b.x * c.y + b.y * c.x;
+}
+// a += conj(b) * c
+template <typename R>
+__device__ __forceinline__ void cjfma(cx<R>& a, cx<R> b, cx<R> c) {
+  a.x += b.x * c.x + b.y * c.y;
+  a.y += b.x * c.y - b.y * c.x;
+}
+
+template <int P>
+struct Tr;
+template <>
+struct Tr<F64> {
+  using R = double;
+};
+template <>
+struct Tr<F32> {
+  using R = float;
+};
+template <>
+struct Tr<F16> {
+  using R = float;
+};
+
+// ------------------------------------------------------------ geometry
+
+__device__ __forceinline__ void eo_coords(const Geom& g, int p, int i, int& x0, int& x1, int& x2, int& x3) {
+  x0 = i / g.Vsh;
+  const int r = i - x0 * g.Vsh;
+  const int t = r / g.L3h;
+  const int x3h = r - t * g.L3h;
+  x1 = t / g.L2;
+  x2 = t - x1 * g.L2;
+  x3 = 2 * x3h + ((p + x0 + x1 + x2) & 1);
+}
+
+__device__ __forceinline__ int eo_index(const Geom& g, int x0, int x1, int x2, int x3) {
+  return (((x0 * g.L1 + x1) * g.L2 + x2) * g.L3 + x3) >> 1;
+}
+
+// Blocks are handed to the 8 XCDs round-robin; give each XCD a contiguous
+// range of tiles so that neighbouring sites share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int xcd = b & 7, k = b >> 3;
+  return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+// ------------------------------------------------------------ spinors
+
+template <int P>
+struct SpinorIO;
+
+template <>
+struct SpinorIO<F64> {
+  template <typename R>
+  __device__ static __forceinline__ void load(const SpinorRef& f, int slot, int i, int Vh, cx<R> (&s)[12]) {
+    const double2* b = static_cast<const double2*>(f.data) + (long)slot * f.slot_stride;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const double2 v = b[(long)c * Vh + i];
+      s[c] = cx<R>{(R)v.x, (R)v.y};
+    }
+  }
+  template <typename R>
+  __device__ static __forceinline__ void store(const SpinorRef& f, int slot, int i, int Vh, const cx<R> (&s)[12]) {
+    double2* b = static_cast<double2*>(f.data) + (long)slot * f.slot_stride;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) b[(long)c * Vh + i] = make_double2((double)s[c].x, (double)s[c].y);
+  }
+};
+
+template <>
+struct SpinorIO<F32> {
+  template <typename R>
+  __device__ static __forceinline__ void load(const SpinorRef& f, int slot, int i, int Vh, cx<R> (&s)[12]) {
+    const float4* b = static_cast<const float4*>(f.data) + (long)slot * f.slot_stride;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float4 v = b[(long)k * Vh + i];
+      s[2 * k] = cx<R>{(R)v.x, (R)v.y};
+      s[2 * k + 1] = cx<R>{(R)v.z, (R)v.w};
+    }
+  }
+  template <typename R>
+  __device__ static __forceinline__ void store(const SpinorRef& f, int slot, int i, int Vh, const cx<R> (&s)[12]) {
+    float4* b = static_cast<float4*>(f.data) + (long)slot * f.slot_stride;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      b[(long)k * Vh + i] = make_float4((float)s[2 * k].x, (float)s[2 * k].y, (float)s[2 * k + 1].x,
+                                        (float)s[2 * k + 1].y);
+  }
+};
+
+__device__ __forceinline__ float2 h2f(unsigned u) {
+  __half2 h = *reinterpret_cast<__half2*>(&u);
+  return __half22float2(h);
+}
+__device__ __forceinline__ unsigned f2h(float a, float b) {
+  __half2 h = __floats2half2_rn(a, b);
+  return *reinterpret_cast<unsigned*>(&h);
+}
+
+template <>
+struct SpinorIO<F16> {
+  template <typename R>
+  __device__ static __forceinline__ void load(const SpinorRef& f, int slot, int i, int Vh, cx<R> (&s)[12]) {
+    const uint4* b = static_cast<const uint4*>(f.data) + (long)slot * f.slot_stride;
+    const float sc = f.scale[(long)slot * f.scale_stride + i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint4 v = b[(long)k * Vh + i];
+      float2 a0 = h2f(v.x), a1 = h2f(v.y), a2 = h2f(v.z), a3 = h2f(v.w);
+      s[4 * k + 0] = cx<R>{(R)(a0.x * sc), (R)(a0.y * sc)};
+      s[4 * k + 1] = cx<R>{(R)(a1.x * sc), (R)(a1.y * sc)};
+      s[4 * k + 2] = cx<R>{(R)(a2.x * sc), (R)(a2.y * sc)};
+      s[4 * k + 3] = cx<R>{(R)(a3.x * sc), (R)(a3.y * sc)};
+    }
+  }
+  template <typename R>
+  __device__ static __forceinline__ void store(const SpinorRef& f, int slot, int i, int Vh, const cx<R> (&s)[12]) {
+    uint4* b = static_cast<uint4*>(f.data) + (long)slot * f.slot_stride;
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf((float)s[c].x), fabsf((float)s[c].y)));
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+    f.scale[(long)slot * f.scale_stride + i] = m;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint4 v;
+      v.x = f2h((float)s[4 * k + 0].x * inv, (float)s[4 * k + 0].y * inv);
+      v.y = f2h((float)s[4 * k + 1].x * inv, (float)s[4 * k + 1].y * inv);
+      v.z = f2h((float)s[4 * k + 2].x * inv, (float)s[4 * k + 2].y * inv);
+      v.w = f2h((float)s[4 * k + 3].x * inv, (float)s[4 * k + 3].y * inv);
+      b[(long)k * Vh + i] = v;
+    }
+  }
+};
+
+// ------------------------------------------------------------ links
+
+template <int P>
+struct LinkIO;
+template <>
+struct LinkIO<F64> {
+  template <typename R>
+  __device__ static __forceinline__ void load(const void* base, int mu, int i, int Vh, cx<R> (&u)[9]) {
+    const double2* b = static_cast<const double2*>(base) + (long)mu * 9 * Vh;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double2 v = b[(long)k * Vh + i];
+      u[k] = cx<R>{(R)v.x, (R)v.y};
+    }
+  }
+};
+template <>
+struct LinkIO<F32> {
+  template <typename R>
+  __device__ static __forceinline__ void load(const void* base, int mu, int i, int Vh, cx<R> (&u)[9]) {
+    const float2* b = static_cast<const float2*>(base) + (long)mu * 9 * Vh;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const float2 v = b[(long)k * Vh + i];
+      u[k] = cx<R>{(R)v.x, (R)v.y};
+    }
+  }
+};
+template <>
+struct LinkIO<F16> {
+  template <typename R>
+  __device__ static __forceinline__ void load(const void* base, int mu, int i, int Vh, cx<R> (&u)[9]) {
+    const unsigned* b = static_cast<const unsigned*>(base) + (long)mu * 9 * Vh;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const float2 v = h2f(b[(long)k * Vh + i]);
+      u[k] = cx<R>{(R)v.x, (R)v.y};
+    }
+  }
+};
+
+// ------------------------------------------------------------ clover blocks
+// Packed Hermitian 6x6: d[0..5] real diagonal, then o[k] for (i<j) row-major.
+
+template <typename R>
+struct HermBlock {
+  R d[6];
+  cx<R> o[15];
+};
+
+__host__ __device__ constexpr int herm_off(int i, int j) {  // i < j
+  return i * 5 - (i * (i - 1)) / 2 + (j - i - 1);
+}
+
+template <int P>
+struct CloverIO;
+template <>
+struct CloverIO<F64> {
+  template <typename R>
+  __device__ static __forceinline__ void load(const void* base, const float*, int i, int Vh, HermBlock<R> (&B)[2]) {
+    const double2* b = static_cast<const double2*>(base);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double2 v = b[(long)(h * 18 + k) * Vh + i];
+        B[h].d[2 * k] = (R)v.x;
+        B[h].d[2 * k + 1] = (R)v.y;
+      }
+#pragma unroll
+      for (int k = 0; k < 15; ++k) {
+        const double2 v = b[(long)(h * 18 + 3 + k) * Vh + i];
+        B[h].o[k] = cx<R>{(R)v.x, (R)v.y};
+      }
+    }
+  }
+};
+template <>
+struct CloverIO<F32> {
+  template <typename R>
+  __device__ static __forceinline__ void load(const void* base, const float*, int i, int Vh, HermBlock<R> (&B)[2]) {
+    const float4* b = static_cast<const float4*>(base);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float r[36];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const float4 v = b[(long)(h * 9 + k) * Vh + i];
+        r[4 * k] = v.x; r[4 * k + 1] = v.y; r[4 * k + 2] = v.z; r[4 * k + 3] = v.w;
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) B[h].d[k] = (R)r[k];
+#pragma unroll
+      for (int k = 0; k < 15; ++k) B[h].o[k] = cx<R>{(R)r[6 + 2 * k], (R)r[7 + 2 * k]};
+    }
+  }
+};
+template <>
+struct CloverIO<F16> {
+  template <typename R>
+  __device__ static __forceinline__ void load(const void* base, const float* scale, int i, int Vh,
+                                              HermBlock<R> (&B)[2]) {
+    const uint4* b = static_cast<const uint4*>(base);
+    const float sc = scale[i];
+    float r[72];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const uint4 v = b[(long)k * Vh + i];
+      float2 a0 = h2f(v.x), a1 = h2f(v.y), a2 = h2f(v.z), a3 = h2f(v.w);
+      r[8 * k + 0] = a0.x; r[8 * k + 1] = a0.y; r[8 * k + 2] = a1.x; r[8 * k + 3] = a1.y;
+      r[8 * k + 4] = a2.x; r[8 * k + 5] = a2.y; r[8 * k + 6] = a3.x; r[8 * k + 7] = a3.y;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) B[h].d[k] = (R)(r[36 * h + k] * sc);
+#pragma unroll
+      for (int k = 0; k < 15; ++k) B[h].o[k] = cx<R>{(R)(r[36 * h + 6 + 2 * k] * sc), (R)(r[36 * h + 7 + 2 * k] * sc)};
+    }
+  }
+};
+
+// y = (B + shift) x on one chirality block (components 6h .. 6h+5 of the spinor)
+template <typename R>
+__device__ __forceinline__ void herm_apply(const HermBlock<R>& B, R shift, const cx<R>* x, cx<R>* y) {
+#pragma unroll
+  for (int r = 0; r < 6; ++r) y[r] = (B.d[r] + shift) * x[r];
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = r + 1; c < 6; ++c) {
+      const cx<R> a = B.o[herm_off(r, c)];
+      cfma(y[r], a, x[c]);   // A_rc x_c
+      cjfma(y[c], a, x[r]);  // A_cr = conj(A_rc)
+    }
+}
+
+// ------------------------------------------------------------ reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// complex a / b
+__device__ __forceinline__ void cdiv(const double* a, const double* b, double* out) {
+  const double den = b[0] * b[0] + b[1] * b[1];
+  const double re = (a[0] * b[0] + a[1] * b[1]) / den;
+  const double im = (a[1] * b[0] - a[0] * b[1]) / den;
+  out[0] = re;
+  out[1] = im;
+}
+
+// Solver finalisers: turn the folded sums of one slot into its scalars.
+__device__ inline void run_finaliser(const ReduceRef& red, int slot, const double (&s)[4]) {
+  if (red.fin == FIN_STORE) {
+    for (int k = 0; k < 4; ++k) red.out_sums[slot * 4 + k] = s[k];
+    return;
+  }
+  SlotScalars& c = red.sc[slot];
+  switch (red.fin) {
+    case FIN_BICG_ALPHA: {
+      if (s[0] == 0.0 && s[1] == 0.0) {
+        c.breakdown = 2;
+        c.alpha[0] = c.alpha[1] = 0.0;
+      } else {
+        cdiv(c.rho, s, c.alpha);
+      }
+      break;
+    }
+    case FIN_BICG_OMEGA: {
+      if (s[2] > 0.0) {
+        c.omega[0] = s[0] / s[2];
+        c.omega[1] = s[1] / s[2];
+      } else {
+        c.omega[0] = c.omega[1] = 0.0;
+      }
+      break;
+    }
+    case FIN_BICG_RHO: {
+      c.rr = s[2];
+      const double mag = sqrt(s[0] * s[0] + s[1] * s[1]);
+      if (!(mag > 1e-14 * sqrt(c.rh2 * s[2]))) c.breakdown = 1;
+      if (c.omega[0] == 0.0 && c.omega[1] == 0.0) c.breakdown = 3;
+      if (c.breakdown == 0) {
+        double q[2], w[2];
+        cdiv(s, c.rho, q);          // rho_new / rho
+        cdiv(c.alpha, c.omega, w);  // alpha / omega
+        c.beta[0] = q[0] * w[0] - q[1] * w[1];
+        c.beta[1] = q[0] * w[1] + q[1] * w[0];
+      } else {
+        c.beta[0] = c.beta[1] = 0.0;
+      }
+      c.rho[0] = s[0];
+      c.rho[1] = s[1];
+      break;
+    }
+    case FIN_BICG_INIT: {
+      c.rho[0] = s[0];
+      c.rho[1] = 0.0;
+      c.rr = s[0];
+      c.rh2 = s[0];
+      c.alpha[0] = c.omega[0] = 1.0;
+      c.alpha[1] = c.omega[1] = 0.0;
+      c.beta[0] = c.beta[1] = 0.0;
+      c.breakdown = 0;
+      break;
+    }
+    case FIN_CG_ALPHA:
+      c.cg_a = s[0] > 0.0 ? c.zz / s[0] : 0.0;
+      break;
+    case FIN_CG_BETA:
+      c.cg_b = c.zz > 0.0 ? s[0] / c.zz : 0.0;
+      c.zz = s[0];
+      break;
+    case FIN_CG_INIT:
+      c.zz = s[0];
+      c.breakdown = 0;
+      break;
+    case FIN_RR:
+      c.rr = s[0];
+      break;
+    default:
+      break;
+  }
+}
+
+// Sum nv values over the block (fixed tree), write the block partial of the
+// slot, and let the last block of the slot fold all partials in block order
+// and run the finaliser.  Deterministic for a fixed launch shape, and a slot's
+// result depends only on that slot's data.  Every thread of the block must
+// call this (no early return before it).
+__device__ inline void block_reduce_finalize(const ReduceRef& red, int nv, double (&v)[4], int slot, int block,
+                                             int nblocks) {
+  __shared__ double lds[4][kBlock / 64];
+  __shared__ int is_last;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < nv; ++k) {
+    const double w = wave_sum(v[k]);
+    if (lane == 0) lds[k][wid] = w;
+  }
+  __syncthreads();
+  double* part = red.partials + (long)slot * nblocks * 4;
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < nv; ++k) {
+      double t = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) t += lds[k][w];
+      st_agent(part + (long)block * 4 + k, t);
+    }
+    __threadfence();
+    const unsigned prev = atomicAdd(&red.counters[slot], 1u);
+    is_last = (prev == (unsigned)(nblocks - 1));
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += kBlock)
+    for (int k = 0; k < nv; ++k) acc[k] += ld_agent(part + (long)b * 4 + k);
+  __syncthreads();
+  for (int k = 0; k < nv; ++k) {
+    const double w = wave_sum(acc[k]);
+    if (lane == 0) lds[k][wid] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < nv; ++k)
+      for (int w = 0; w < kBlock / 64; ++w) s[k] += lds[k][w];
+    run_finaliser(red, slot, s);
+    atomicExch(&red.counters[slot], 0u);
+  }
+}
+
+}  // namespace dp

@@ -1,0 +1,258 @@
+// The alpha-hop Wilson kernel with clover epilogues.
+//
+// For an output site x of parity p it computes the hopping term of the
+// preconditioned operator D' = alpha (D + M) alpha^-1 (eq. linsysprec),
+//
+//   H psi(x) = -1/2 sum_mu [ c+_mu(x) (1 - gamma_mu) U_mu(x) psi(x+mu)
+//                          + c-_mu(x) (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu) ]
+//
+// where the spatial c = 1 and the time factors are the ratios of the modified
+// time derivatives (heavy-quark section): c+_0(x) = alpha(x0)/alpha(x0+1) and
+// c-_0(x) = alpha(x0)/alpha(x0-1), with the fermion boundary sign folded in at
+// the wrap-around (the boundary rule eq. redeftbc reduces to exactly this).
+// The adjoint hop (dag = 1) swaps the projectors and uses the reciprocal
+// ratios; it is the hopping part of gamma5 D'(1/alpha) gamma5 = D'(alpha)^+.
+//
+// Spin projection in the chiral basis, with psi = (u0, u1, l0, l1) in spin and
+// s = +1 for (1 - gamma_mu), s = -1 for (1 + gamma_mu):
+//   mu = 0: h = u + s l,                 lower = s h
+//   mu = k: h = u + s (i sigma_k) l,     lower = -s (i sigma_k) h
+// so only the two upper spins are multiplied by the link.
+//
+// One thread per output site and right-hand side; blockIdx.y is the slot.
+#include "dp_device.h"
+
+namespace dp {
+
+namespace {
+
+template <typename R>
+struct Half {
+  cx<R> h[2][3];
+};
+
+template <int MU, typename R>
+__device__ __forceinline__ void project(const cx<R> (&s)[12], R sg, Half<R>& o) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const cx<R> u0 = s[a], u1 = s[3 + a], l0 = s[6 + a], l1 = s[9 + a];
+    if constexpr (MU == 0) {
+      o.h[0][a] = u0 + sg * l0;
+      o.h[1][a] = u1 + sg * l1;
+    } else if constexpr (MU == 1) {  // i sigma_1 l = (i l1, i l0)
+      o.h[0][a] = u0 + sg * ti(l1);
+      o.h[1][a] = u1 + sg * ti(l0);
+    } else if constexpr (MU == 2) {  // i sigma_2 l = (l1, -l0)
+      o.h[0][a] = u0 + sg * l1;
+      o.h[1][a] = u1 - sg * l0;
+    } else {  // i sigma_3 l = (i l0, -i l1)
+      o.h[0][a] = u0 + sg * ti(l0);
+      o.h[1][a] = u1 - sg * ti(l1);
+    }
+  }
+}
+
+// acc += c * (1 - s gamma_mu)-reconstruction of the link-multiplied half spinor
+template <int MU, typename R>
+__device__ __forceinline__ void accumulate(cx<R> (&acc)[12], const Half<R>& w, R sg, R c) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const cx<R> w0 = c * w.h[0][a], w1 = c * w.h[1][a];
+    acc[a] = acc[a] + w0;
+    acc[3 + a] = acc[3 + a] + w1;
+    if constexpr (MU == 0) {
+      acc[6 + a] = acc[6 + a] + sg * w0;
+      acc[9 + a] = acc[9 + a] + sg * w1;
+    } else if constexpr (MU == 1) {  // -s i sigma_1 w = -s (i w1, i w0)
+      acc[6 + a] = acc[6 + a] - sg * ti(w1);
+      acc[9 + a] = acc[9 + a] - sg * ti(w0);
+    } else if constexpr (MU == 2) {  // -s i sigma_2 w = -s (w1, -w0)
+      acc[6 + a] = acc[6 + a] - sg * w1;
+      acc[9 + a] = acc[9 + a] + sg * w0;
+    } else {  // -s i sigma_3 w = -s (i w0, -i w1)
+      acc[6 + a] = acc[6 + a] - sg * ti(w0);
+      acc[9 + a] = acc[9 + a] + sg * ti(w1);
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void link_mul(const cx<R> (&u)[9], const Half<R>& h, Half<R>& o) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<R> t = cmul(u[3 * a], h.h[s][0]);
+      cfma(t, u[3 * a + 1], h.h[s][1]);
+      cfma(t, u[3 * a + 2], h.h[s][2]);
+      o.h[s][a] = t;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void link_dag_mul(const cx<R> (&u)[9], const Half<R>& h, Half<R>& o) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<R> t = cjmul(u[a], h.h[s][0]);
+      cjfma(t, u[3 + a], h.h[s][1]);
+      cjfma(t, u[6 + a], h.h[s][2]);
+      o.h[s][a] = t;
+    }
+}
+
+template <int P, int MU>
+__device__ __forceinline__ void hop_dir(const HopArgs& a, int slot, int i, const int (&x)[4], typename Tr<P>::R cf,
+                                        typename Tr<P>::R cb, typename Tr<P>::R sg,
+                                        cx<typename Tr<P>::R> (&acc)[12]) {
+  using R = typename Tr<P>::R;
+  const Geom& g = a.g;
+  const int L = MU == 0 ? g.T : MU == 1 ? g.L1 : MU == 2 ? g.L2 : g.L3;
+  int y[4] = {x[0], x[1], x[2], x[3]};
+  cx<R> psi[12], u[9];
+  Half<R> h, w;
+  // forward neighbour x + mu
+  y[MU] = x[MU] + 1 == L ? 0 : x[MU] + 1;
+  const int jf = eo_index(g, y[0], y[1], y[2], y[3]);
+  SpinorIO<P>::load(a.in, slot, jf, g.Vh, psi);
+  project<MU>(psi, sg, h);
+  LinkIO<P>::load(a.U_out, MU, i, g.Vh, u);
+  link_mul(u, h, w);
+  accumulate<MU>(acc, w, sg, MU == 0 ? cf : R(1));
+  // backward neighbour x - mu
+  y[MU] = x[MU] == 0 ? L - 1 : x[MU] - 1;
+  const int jb = eo_index(g, y[0], y[1], y[2], y[3]);
+  SpinorIO<P>::load(a.in, slot, jb, g.Vh, psi);
+  project<MU>(psi, -sg, h);
+  LinkIO<P>::load(a.U_in, MU, jb, g.Vh, u);
+  link_dag_mul(u, h, w);
+  accumulate<MU>(acc, w, -sg, MU == 0 ? cb : R(1));
+}
+
+template <int P, int EPI, int RED>
+__global__ void __launch_bounds__(kBlock) hop_kernel(HopArgs a) {
+  using R = typename Tr<P>::R;
+  const Geom& g = a.g;
+  const int slot = blockIdx.y;
+  if (a.slots.mask && !a.slots.mask[slot]) return;  // uniform over the slot's blocks
+  const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  double red[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < g.Vh) {
+    int x[4];
+    eo_coords(g, a.p, i, x[0], x[1], x[2], x[3]);
+    const double* rt = a.slots.ratio + (long)slot * 4 * g.T;
+    const R cf = (R)(a.dag ? rt[2 * g.T + x[0]] : rt[x[0]]);
+    const R cb = (R)(a.dag ? rt[3 * g.T + x[0]] : rt[g.T + x[0]]);
+    const R sg = a.dag ? R(-1) : R(1);
+    cx<R> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = cx<R>{R(0), R(0)};
+    hop_dir<P, 0>(a, slot, i, x, cf, cb, sg, acc);
+    hop_dir<P, 1>(a, slot, i, x, cf, cb, sg, acc);
+    hop_dir<P, 2>(a, slot, i, x, cf, cb, sg, acc);
+    hop_dir<P, 3>(a, slot, i, x, cf, cb, sg, acc);
+
+    cx<R> out[12], xin[12];
+    if constexpr (EPI == EPI_HOP) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) out[c] = R(-0.5) * acc[c];
+    } else if constexpr (EPI == EPI_DIAG) {
+      SpinorIO<P>::load(a.xin, slot, i, g.Vh, xin);
+      HermBlock<R> B[2];
+      CloverIO<P>::load(a.clov.data, a.clov.scale, i, g.Vh, B);
+      const R m4 = (R)a.slots.m4[slot];
+      herm_apply(B[0], m4, &xin[0], &out[0]);
+      herm_apply(B[1], m4, &xin[6], &out[6]);
+      const R hs = (R)(-0.5 * a.sign);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) out[c] = out[c] + hs * acc[c];
+    } else if constexpr (EPI == EPI_SUB) {
+      SpinorIO<P>::load(a.xin, slot, i, g.Vh, xin);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) out[c] = xin[c] + R(0.5) * acc[c];
+    } else {  // EPI_INV, EPI_INV_SUB
+      cx<R> t[12];
+      if constexpr (EPI == EPI_INV_SUB) {
+        SpinorIO<P>::load(a.xin, slot, i, g.Vh, xin);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) t[c] = xin[c] + R(0.5) * acc[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) t[c] = R(-0.5) * acc[c];
+      }
+      HermBlock<R> B[2];
+      const float* sc = a.slots.ainv_scale ? a.slots.ainv_scale[slot] : nullptr;
+      CloverIO<P>::load(a.slots.ainv[slot], sc, i, g.Vh, B);
+      herm_apply(B[0], R(0), &t[0], &out[0]);
+      herm_apply(B[1], R(0), &t[6], &out[6]);
+    }
+    SpinorIO<P>::store(a.out, slot, i, g.Vh, out);
+
+    if constexpr (RED == RED_DOT_EXT) {
+      cx<R> w[12];
+      SpinorIO<P>::load(a.red.w, slot, i, g.Vh, w);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        red[0] += (double)w[c].x * (double)out[c].x + (double)w[c].y * (double)out[c].y;
+        red[1] += (double)w[c].x * (double)out[c].y - (double)w[c].y * (double)out[c].x;
+      }
+    } else if constexpr (RED == RED_TS) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        red[0] += (double)out[c].x * (double)xin[c].x + (double)out[c].y * (double)xin[c].y;
+        red[1] += (double)out[c].x * (double)xin[c].y - (double)out[c].y * (double)xin[c].x;
+        red[2] += (double)out[c].x * (double)out[c].x + (double)out[c].y * (double)out[c].y;
+      }
+    } else if constexpr (RED == RED_NORM) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) red[0] += (double)out[c].x * (double)out[c].x + (double)out[c].y * (double)out[c].y;
+    }
+  }
+  if constexpr (RED != RED_NONE) {
+    const int nv = RED == RED_DOT_EXT ? 2 : RED == RED_TS ? 3 : 1;
+    block_reduce_finalize(a.red, nv, red, slot, blockIdx.x, gridDim.x);
+  }
+}
+
+template <int P, int EPI>
+hipError_t launch_red(const HopArgs& a, dim3 grid, hipStream_t st) {
+  switch (a.red.red) {
+    case RED_NONE: hipLaunchKernelGGL((hop_kernel<P, EPI, RED_NONE>), grid, dim3(kBlock), 0, st, a); break;
+    case RED_DOT_EXT: hipLaunchKernelGGL((hop_kernel<P, EPI, RED_DOT_EXT>), grid, dim3(kBlock), 0, st, a); break;
+    case RED_TS: hipLaunchKernelGGL((hop_kernel<P, EPI, RED_TS>), grid, dim3(kBlock), 0, st, a); break;
+    case RED_NORM: hipLaunchKernelGGL((hop_kernel<P, EPI, RED_NORM>), grid, dim3(kBlock), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_epi(const HopArgs& a, dim3 grid, hipStream_t st) {
+  switch (a.epi) {
+    case EPI_HOP: return launch_red<P, EPI_HOP>(a, grid, st);
+    case EPI_INV: return launch_red<P, EPI_INV>(a, grid, st);
+    case EPI_DIAG: return launch_red<P, EPI_DIAG>(a, grid, st);
+    case EPI_SUB: return launch_red<P, EPI_SUB>(a, grid, st);
+    case EPI_INV_SUB: return launch_red<P, EPI_INV_SUB>(a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+int reduction_blocks(const Geom& g) { return (g.Vh + kBlock - 1) / kBlock; }
+
+hipError_t launch_hop(const HopArgs& a, hipStream_t st) {
+  if (a.nslots <= 0 || a.g.Vh <= 0) return hipErrorInvalidValue;
+  if (a.in.prec != a.out.prec || a.link_prec != a.in.prec) return hipErrorInvalidValue;
+  const dim3 grid(reduction_blocks(a.g), a.nslots);
+  switch (a.in.prec) {
+    case F64: return launch_epi<F64>(a, grid, st);
+    case F32: return launch_epi<F32>(a, grid, st);
+    case F16: return launch_epi<F16>(a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dp

@@ -1,0 +1,152 @@
+// Layout kernels: host-order (x0 slowest, complex128 interleaved) fields to the
+// structure-of-arrays parity layout and back, precision conversion, the source
+// redefinition eta' = alpha eta, the restoration S = S'/alpha and the per-
+// timeslice correlator C_PP(y0) = -sum_y tr[S^+ S] (heavy-quark section,
+// restoration eq. backcorrection in the form C = C'/alpha^2).
+#include "dp_device.h"
+
+namespace dp {
+
+namespace {
+
+__device__ __forceinline__ void lex_coords(const Geom& g, long s, int& x0, int& x1, int& x2, int& x3) {
+  x3 = (int)(s % g.L3);
+  s /= g.L3;
+  x2 = (int)(s % g.L2);
+  s /= g.L2;
+  x1 = (int)(s % g.L1);
+  x0 = (int)(s / g.L1);
+}
+
+template <int P>
+__global__ void gauge_reorder_kernel(Geom g, const double2* __restrict__ U, void* e, void* o) {
+  const long V = 2L * g.Vh;
+  const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  int x0, x1, x2, x3;
+  lex_coords(g, s, x0, x1, x2, x3);
+  const int p = (x0 + x1 + x2 + x3) & 1;
+  const int i = (int)(s >> 1);
+  void* dst = p ? o : e;
+  for (int mu = 0; mu < 4; ++mu)
+    for (int k = 0; k < 9; ++k) {
+      const double2 v = U ? U[(s * 4 + mu) * 9 + k] : make_double2((k % 4 == 0) ? 1.0 : 0.0, 0.0);
+      const long at = (long)(mu * 9 + k) * g.Vh + i;
+      if constexpr (P == F64) {
+        static_cast<double2*>(dst)[at] = v;
+      } else if constexpr (P == F32) {
+        static_cast<float2*>(dst)[at] = make_float2((float)v.x, (float)v.y);
+      } else {
+        static_cast<unsigned*>(dst)[at] = f2h((float)v.x, (float)v.y);
+      }
+    }
+}
+
+// host-order spinors -> FP64 parity field, optionally times alpha(x0)
+__global__ void spinor_import_kernel(Geom g, const double2* __restrict__ aos, long aos_ss, int p, SpinorRef dst,
+                                     const double* __restrict__ amul) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int slot = blockIdx.y;
+  if (i >= g.Vh) return;
+  int x0, x1, x2, x3;
+  eo_coords(g, p, i, x0, x1, x2, x3);
+  const long s = ((long)(x0 * g.L1 + x1) * g.L2 + x2) * g.L3 + x3;
+  const double f = amul ? amul[(long)slot * g.T + x0] : 1.0;
+  const double2* src = aos + slot * aos_ss + s * 12;
+  double2* d = static_cast<double2*>(dst.data) + slot * dst.slot_stride;
+  for (int c = 0; c < 12; ++c) {
+    const double2 v = src[c];
+    d[(long)c * g.Vh + i] = make_double2(f * v.x, f * v.y);
+  }
+}
+
+// FP64 parity fields -> host-order spinors, optionally divided by alpha(x0)
+__global__ void spinor_export_kernel(Geom g, SpinorRef e, SpinorRef o, const double* __restrict__ adiv,
+                                     double2* __restrict__ aos, long aos_ss) {
+  const long V = 2L * g.Vh;
+  const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int slot = blockIdx.y;
+  if (s >= V) return;
+  int x0, x1, x2, x3;
+  lex_coords(g, s, x0, x1, x2, x3);
+  const int p = (x0 + x1 + x2 + x3) & 1;
+  const int i = (int)(s >> 1);
+  const SpinorRef& f = p ? o : e;
+  const double2* src = static_cast<const double2*>(f.data) + slot * f.slot_stride;
+  const double inv = adiv ? 1.0 / adiv[(long)slot * g.T + x0] : 1.0;
+  double2* d = aos + slot * aos_ss + s * 12;
+  for (int c = 0; c < 12; ++c) {
+    const double2 v = src[(long)c * g.Vh + i];
+    d[c] = make_double2(v.x * inv, v.y * inv);
+  }
+}
+
+// One block per (timeslice, slot): -sum over both parities of |psi|^2 / alpha^2.
+__global__ void __launch_bounds__(kBlock) cpp_kernel(Geom g, SpinorRef e, SpinorRef o,
+                                                     const double* __restrict__ alpha, const int* __restrict__ x0src,
+                                                     double* __restrict__ cpp) {
+  const int x0 = blockIdx.x, slot = blockIdx.y;
+  __shared__ double lds[kBlock / 64];
+  double acc = 0.0;
+  for (int par = 0; par < 2; ++par) {
+    const SpinorRef& f = par ? o : e;
+    const double2* src = static_cast<const double2*>(f.data) + slot * f.slot_stride;
+    for (int k = threadIdx.x; k < g.Vsh; k += kBlock) {
+      const int i = x0 * g.Vsh + k;
+      for (int c = 0; c < 12; ++c) {
+        const double2 v = src[(long)c * g.Vh + i];
+        acc += v.x * v.x + v.y * v.y;
+      }
+    }
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) s += lds[w];
+    const double a = alpha ? alpha[(long)slot * g.T + x0] : 1.0;
+    const int t = ((x0 - (x0src ? x0src[slot] : 0)) % g.T + g.T) % g.T;
+    cpp[(long)slot * g.T + t] = -s / (a * a);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gauge_reorder(const Geom& g, const double2* U_aos, void* U_eo[2], int prec, hipStream_t st) {
+  const long V = 2L * g.Vh;
+  const dim3 grid((unsigned)((V + kBlock - 1) / kBlock));
+  switch (prec) {
+    case F64: hipLaunchKernelGGL(gauge_reorder_kernel<F64>, grid, dim3(kBlock), 0, st, g, U_aos, U_eo[0], U_eo[1]); break;
+    case F32: hipLaunchKernelGGL(gauge_reorder_kernel<F32>, grid, dim3(kBlock), 0, st, g, U_aos, U_eo[0], U_eo[1]); break;
+    case F16: hipLaunchKernelGGL(gauge_reorder_kernel<F16>, grid, dim3(kBlock), 0, st, g, U_aos, U_eo[0], U_eo[1]); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_spinor_import(const Geom& g, const double2* aos, int nslots, long aos_ss, int p, SpinorRef dst,
+                                const double* alpha_mul, hipStream_t st) {
+  if (dst.prec != F64 || nslots <= 0) return hipErrorInvalidValue;
+  const dim3 grid((g.Vh + kBlock - 1) / kBlock, nslots);
+  hipLaunchKernelGGL(spinor_import_kernel, grid, dim3(kBlock), 0, st, g, aos, aos_ss, p, dst, alpha_mul);
+  return hipGetLastError();
+}
+
+hipError_t launch_spinor_export(const Geom& g, SpinorRef even, SpinorRef odd, int nslots, const double* alpha_div,
+                                double2* aos, long aos_ss, hipStream_t st) {
+  if (even.prec != F64 || odd.prec != F64 || nslots <= 0) return hipErrorInvalidValue;
+  const long V = 2L * g.Vh;
+  const dim3 grid((unsigned)((V + kBlock - 1) / kBlock), nslots);
+  hipLaunchKernelGGL(spinor_export_kernel, grid, dim3(kBlock), 0, st, g, even, odd, alpha_div, aos, aos_ss);
+  return hipGetLastError();
+}
+
+hipError_t launch_cpp(const Geom& g, SpinorRef even, SpinorRef odd, int nslots, const double* alpha, const int* x0src,
+                      double* cpp, hipStream_t st) {
+  if (even.prec != F64 || odd.prec != F64 || nslots <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cpp_kernel, dim3(g.T, nslots), dim3(kBlock), 0, st, g, even, odd, alpha, x0src, cpp);
+  return hipGetLastError();
+}
+
+}  // namespace dp
