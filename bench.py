@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Benchmark of the distance-preconditioned Wilson-clover solve on one MI355X.
+
+One step = one 12-column point-source propagator of the 24^3 x 48 workload
+(synthetic SU(3) field, eps = 0.25, c_sw = 1.6, M = 0.5, the paper's
+periodic-time profile with alpha0 = 0.4, r = 1e-11): source redefinition,
+Schur right-hand side, the mixed-precision solve (FP32 inner BiCGStab, FP64
+residuals and updates), odd-site reconstruction, restoration S = S'/alpha
+and C_PP, with eta and S resident in HBM.  `value` counts solved
+right-hand sides per second.  The same steps on the FP64 path, the per-
+timeslice C_PP agreement of the two, the dominant kernel's roofline (from
+HIP events on the library's stream) and the CPU oracle on one column are
+reported on the same line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Dslash HBM GB/s (% roofline); solves/s + p99 latency, mixed vs FP64 at r=1e-11"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="su3_24c48")
+    ap.add_argument("--precision", default="f32", choices=["f32", "f16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md on sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1006_4028_amd as dp
+    import synth
+
+    cfg = synth.config(args.workload)
+    dims, M, csw, r = cfg["dims"], cfg["masses"][0], cfg["csw"], cfg["r"]
+    alpha0 = cfg["alpha0s"][-1]
+    ncols = 12
+    log(f"workload {args.workload} dims={dims}: generating the field")
+    U = synth.gauge_su3(dims, cfg["eps"], cfg["seed"])
+    alpha = synth.alpha_table(cfg["profile"], dims[0], alpha0)
+    eta = synth.point_sources_12(dims, (0, 0, 0, 0), ncols)
+
+    dev = torch.device("cuda:0")
+    eta_t = torch.from_numpy(eta.reshape(ncols, -1)).to(dev)
+    S_t = torch.empty_like(eta_t)
+    L = dp.Lattice(dims)
+    L.set_gauge(U)
+    L.set_clover(csw)
+    L.set_mass(M)
+    L.set_alpha(alpha)
+
+    def run(precision, steps, warmup, timing=False):
+        for _ in range(warmup):
+            L.solve_dev(eta_t, S_t, r=r, precision=precision, ncols_group=ncols)
+        L.set_timing(timing)
+        lat, infos, cpp = [], None, None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ts = time.perf_counter()
+            cpp, infos = L.solve_dev(eta_t, S_t, r=r, precision=precision, ncols_group=ncols)
+            lat.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        stats = L.timing() if timing else {}
+        L.set_timing(False)
+        return total, lat, infos, cpp, stats
+
+    log(f"mixed path ({args.precision} inner): {args.warmup} warmup + {args.steps} timed steps")
+    total, lat, infos, cpp_mixed, stats = run(args.precision, args.steps, args.warmup, timing=True)
+    for i in infos:
+        assert i["status"] == 0 and i["true_res"] <= r, i
+    solves_per_s = ncols * args.steps / total
+    lat_ms = sorted(1e3 * x for x in lat)
+
+    def pct(v, q):
+        k = min(len(v) - 1, max(0, int(round(q * (len(v) - 1)))))
+        return v[k]
+
+    # dominant kernel: the hop variant with the most total time
+    hops = {k: v for k, v in stats.items() if k.startswith("hop_")}
+    name, st = max(hops.items(), key=lambda kv: kv[1]["ms"])
+    avg_ms = st["ms"] / st["launches"]
+    gbs = st["bytes"] / st["launches"] / (avg_ms * 1e-3) / 1e9
+    all_hop_ms = sum(v["ms"] for v in hops.values())
+    all_hop_gbs = sum(v["bytes"] for v in hops.values()) / (all_hop_ms * 1e-3) / 1e9
+    log(f"  {solves_per_s:.1f} solves/s, p50 {pct(lat_ms, 0.5):.2f} ms, p99 {pct(lat_ms, 0.99):.2f} ms, "
+        f"iters {[i['iters'] for i in infos]}")
+    for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"]):
+        log(f"  {k:18s} launches {v['launches']:6d} avg {1e3 * v['ms'] / v['launches']:8.1f} us "
+            f"{v['bytes'] / (v['ms'] * 1e-3) / 1e9 if v['ms'] > 0 else 0:8.1f} GB/s")
+
+    fp64 = None
+    if not args.no_fp64:
+        log(f"FP64 path: 1 warmup + {args.steps} timed steps")
+        t64, lat64, infos64, cpp64, _ = run("f64", args.steps, 1)
+        for i in infos64:
+            assert i["status"] == 0 and i["true_res"] <= r, i
+        lat64_ms = sorted(1e3 * x for x in lat64)
+        cpp_err = float(np.abs(cpp_mixed[0] / cpp64[0] - 1).max())
+        fp64 = {"value": round(ncols * args.steps / t64, 3), "unit": "solves/s",
+                "p50_ms": round(pct(lat64_ms, 0.5), 3), "p99_ms": round(pct(lat64_ms, 0.99), 3),
+                "iters": [i["iters"] for i in infos64],
+                "mixed_vs_fp64_cpp_max_rel_err_per_timeslice": cpp_err}
+        log(f"  {fp64['value']} solves/s; mixed/FP64 C_PP max rel err per timeslice {cpp_err:.2e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("CPU oracle: one column of the same workload, FP64 BiCGStab to r")
+        C = oracle.clover(U, csw)
+        t0 = time.perf_counter()
+        _, info_or = oracle.solve(U, C, M, eta[0], alpha=alpha, r=r)
+        t_or = time.perf_counter() - t0
+        cpu = {"value": round(1.0 / t_or, 6), "unit": "solves/s", "cores": oracle.get_threads(), "kind": "oracle",
+               "sample": f"1 of the {ncols} columns, full-lattice FP64 BiCGStab, {info_or['iters']} iterations, "
+                         f"{t_or:.1f} s"}
+        log(f"  {t_or:.1f} s for one column on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": round(solves_per_s, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * total / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 inner / f64 outer" if args.precision == "f32" else "f16 storage inner / f64 outer",
+        "data": "synthetic (seeded SU(3) field, point sources)",
+        "config": {"workload": f"{args.workload}: {dims[1]}^3x{dims[0]} clover c_sw={csw}, M={M}, "
+                               f"{cfg['profile']} alpha0={alpha0}, {ncols} point-source columns per step, r={r}",
+                   "global_batch": ncols, "parallelism": "single GPU"},
+        "p50_ms": round(pct(lat_ms, 0.5), 3),
+        "p99_ms": round(pct(lat_ms, 0.99), 3),
+        "iters": [i["iters"] for i in infos],
+        "fp64": fp64,
+        "speedup_vs_fp64": round(solves_per_s / fp64["value"], 3) if fp64 else None,
+        "roofline": {"bound": "hbm", "kernel": name, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_us": round(1e3 * avg_ms, 2),
+                     "alg_bytes_per_launch": st["bytes"] / st["launches"],
+                     "all_hop_kernels_GBps": round(all_hop_gbs, 1)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    L.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -151,6 +151,22 @@ int dp_solve(dp_ctx* ctx, const double* eta, int nrhs, const dp_params* p, doubl
 int dp_solve_dev(dp_ctx* ctx, const void* eta_dev, int nrhs, const dp_params* p, void* S_dev, double* cpp,
                  dp_info* info, void* hip_stream);
 
+/* Per-kernel timing of the library's own launches.  dp_set_timing(ctx, 1)
+ * clears the statistics and brackets every later kernel launch of the ctx
+ * with HIP events on the stream it runs on; dp_get_timing copies up to `max`
+ * entries (one per kernel variant, e.g. "hop_f32_diag") and sets *count to
+ * the number available.  bytes and flops are algorithmic: each link, clover
+ * block and input spinor counted once per launch, each output once. */
+typedef struct {
+  char name[32];
+  long long launches;
+  double ms;    /* summed event-to-event time */
+  double bytes; /* summed algorithmic HBM bytes */
+  double flops; /* summed algorithmic flops */
+} dp_kernel_stat;
+int dp_set_timing(dp_ctx* ctx, int enable);
+int dp_get_timing(dp_ctx* ctx, dp_kernel_stat* out, int max, int* count);
+
 /* Device bytes a context would hold for the gauge field and clover of a
  * lattice, plus the solver work space for nrhs right-hand sides at the given
  * precision, plus one per-mass inverse per new mass. */

@@ -105,6 +105,19 @@ class Lattice:
         self._check(self._L.dp_apply(self._h, _ptr(psi), _ptr(out), flags))
         return out
 
+    # ------------------------------------------------------------ timing
+    def set_timing(self, enable=True):
+        self._check(self._L.dp_set_timing(self._h, int(bool(enable))))
+
+    def timing(self):
+        """Per-kernel statistics: {name: dict(launches, ms, bytes, flops)}."""
+        n = ctypes.c_int(0)
+        self._check(self._L.dp_get_timing(self._h, None, 0, ctypes.byref(n)))
+        arr = (L.dp_kernel_stat * max(n.value, 1))()
+        self._check(self._L.dp_get_timing(self._h, arr, n.value, ctypes.byref(n)))
+        return {a.name.decode(): dict(launches=a.launches, ms=a.ms, bytes=a.bytes, flops=a.flops)
+                for a in arr[:n.value]}
+
     # ------------------------------------------------------------ solves
     @staticmethod
     def _params(r, solver, precision, max_iter, delta, x0_src, ncols_group):

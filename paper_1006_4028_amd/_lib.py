@@ -29,7 +29,7 @@ DP_APPLY_SCHUR, DP_APPLY_F32, DP_APPLY_F16 = 8, 16, 32
 EXPORTED = [
     "dp_create", "dp_destroy", "dp_last_error", "dp_set_gauge", "dp_set_gauge_dev", "dp_set_clover",
     "dp_set_clover_field", "dp_set_mass", "dp_set_kappa", "dp_set_alpha", "dp_apply", "dp_solve",
-    "dp_solve_dev", "dp_footprint_bytes",
+    "dp_solve_dev", "dp_footprint_bytes", "dp_set_timing", "dp_get_timing",
 ]
 
 
@@ -43,6 +43,11 @@ class dp_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("outer", ctypes.c_int),
                 ("hop_calls", ctypes.c_int), ("restarts", ctypes.c_int), ("true_res", ctypes.c_double),
                 ("seconds", ctypes.c_double)]
+
+
+class dp_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_longlong), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
 class DPError(RuntimeError):
@@ -81,5 +86,7 @@ def lib():
                                ctypes.POINTER(dp_info), vp]
     L.dp_footprint_bytes.argtypes = [ip, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.dp_footprint_bytes.restype = ctypes.c_longlong
+    L.dp_set_timing.argtypes = [vp, ctypes.c_int]
+    L.dp_get_timing.argtypes = [vp, ctypes.POINTER(dp_kernel_stat), ctypes.c_int, ip]
     _lib = L
     return L

@@ -1,5 +1,6 @@
 // Host runtime of libdp: device buffers, the context, and the batched solver.
 #pragma once
+#include <map>
 #include <string>
 #include <vector>
 
@@ -126,6 +127,22 @@ struct dp_ctx {
 
   dp::Workspace ws;
   dp::DevBuf scratch_aos, bad_flag;
+
+  // per-launch HIP-event timing of the library's kernels (dp_set_timing)
+  struct KStat {
+    long long launches = 0;
+    double ms = 0.0, bytes = 0.0, flops = 0.0;
+  };
+  struct Pending {
+    std::string name;
+    double bytes, flops;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<Pending> pending;
+  std::map<std::string, KStat> kstats;
+  std::map<const void*, int> mask_count;  // active slots of each device mask
 
   ~dp_ctx();
 };

@@ -67,6 +67,11 @@ hipError_t Field::alloc(const Geom& g, int prec_, int nslots_) {
 }
 
 dp_ctx::~dp_ctx() {
+  for (auto& q : pending) {
+    (void)hipEventDestroy(q.a);
+    (void)hipEventDestroy(q.b);
+  }
+  for (auto e : ev_free) (void)hipEventDestroy(e);
   for (auto* m : masses) delete m;
   if (stream) (void)hipStreamDestroy(stream);
 }
@@ -256,6 +261,9 @@ int upload_slot_tables(dp_ctx* c, int nslots, const double* alpha, MassEntry* me
 }
 
 int upload_mask(dp_ctx* c, DevBuf& dst, const std::vector<int>& m, int slot_in_staging) {
+  int cnt = 0;
+  for (int v : m) cnt += v != 0;
+  c->mask_count[dst.p] = cnt;
   int* h = c->ws.h_mask.as<int>() + (size_t)slot_in_staging * c->ws.nslots;
   std::memcpy(h, m.data(), sizeof(int) * m.size());
   DP_HIP(c, hipMemcpyAsync(dst.p, h, sizeof(int) * m.size(), hipMemcpyHostToDevice, c->stream));
@@ -285,6 +293,89 @@ ReduceRef reduce_ref(dp_ctx* c, int red, int fin) {
   return r;
 }
 
+// ----------------------------------------------------------- launch timing
+
+const char* prec_name(int p) { return p == F64 ? "f64" : p == F32 ? "f32" : "f16"; }
+
+int active_slots(dp_ctx* c, const int* mask, int nslots) {
+  auto it = c->mask_count.find(mask);
+  return it == c->mask_count.end() ? nslots : it->second;
+}
+
+int timing_begin(dp_ctx* c, hipEvent_t* a) {
+  if (!c->timing) return DP_OK;
+  if (c->ev_free.size() < 2) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      DP_HIP(c, hipEventCreate(&e));
+      c->ev_free.push_back(e);
+    }
+  }
+  *a = c->ev_free.back();
+  c->ev_free.pop_back();
+  DP_HIP(c, hipEventRecord(*a, c->stream));
+  return DP_OK;
+}
+
+int timing_end(dp_ctx* c, hipEvent_t a, const std::string& name, double bytes, double flops) {
+  if (!c->timing) return DP_OK;
+  hipEvent_t b = c->ev_free.back();
+  c->ev_free.pop_back();
+  DP_HIP(c, hipEventRecord(b, c->stream));
+  c->pending.push_back({name, bytes, flops, a, b});
+  return DP_OK;
+}
+
+// fold finished launches into the per-kernel statistics (after a stream sync)
+int timing_harvest(dp_ctx* c) {
+  for (auto& q : c->pending) {
+    float ms = 0.f;
+    DP_HIP(c, hipEventSynchronize(q.b));
+    DP_HIP(c, hipEventElapsedTime(&ms, q.a, q.b));
+    auto& k = c->kstats[q.name];
+    k.launches++;
+    k.ms += ms;
+    k.bytes += q.bytes;
+    k.flops += q.flops;
+    c->ev_free.push_back(q.a);
+    c->ev_free.push_back(q.b);
+  }
+  c->pending.clear();
+  return DP_OK;
+}
+
+// Algorithmic HBM bytes of one hop launch: each link, clover block and input
+// spinor once, each output once.  Per output site: 8 links (144 reals, shared by
+// the slots), per active slot the input (24) and output (24) spinors, the
+// clover block pair (72 reals) for the epilogues that use it, the epilogue
+// input (24 per slot) and the dot partner (24 per slot); FP16 adds the 4-byte
+// per-site scales.  Flops: 1320 per site and slot for the hop, 552 for a
+// clover block pair, 48 for the epilogue axpy and 8-16 for a fused dot.
+void hop_cost(dp_ctx* c, int prec, int epi, int red, int nact, double* bytes, double* flops) {
+  const double b = prec == F64 ? 8.0 : prec == F32 ? 4.0 : 2.0;
+  const double sc = prec == F16 ? 4.0 : 0.0;
+  const double Vh = c->g.Vh;
+  double site = 144 * b;
+  double slot = 2 * (24 * b + sc);
+  double fl = 1320;
+  if (epi == EPI_INV || epi == EPI_INV_SUB || epi == EPI_DIAG) {
+    site += 72 * b + sc;
+    fl += 552;
+  }
+  if (epi == EPI_DIAG || epi == EPI_SUB || epi == EPI_INV_SUB) {
+    slot += 24 * b + sc;
+    fl += 48;
+  }
+  if (red == RED_DOT_EXT) {
+    slot += 24 * b + sc;
+    fl += 96;
+  } else if (red != RED_NONE) {
+    fl += 96;
+  }
+  *bytes = Vh * (site + nact * slot);
+  *flops = Vh * nact * fl;
+}
+
 // one hop launch; p = output parity
 int hop(dp_ctx* c, int nslots, int prec, int p, int dag, int epi, double sign, const Field& in, const Field& out,
         const Field* xin, const int* mask, int red = RED_NONE, int fin = FIN_NONE, const Field* w = nullptr) {
@@ -305,7 +396,16 @@ int hop(dp_ctx* c, int nslots, int prec, int p, int dag, int epi, double sign, c
   a.red = reduce_ref(c, red, fin);
   if (w) a.red.w = w->ref();
   a.nslots = nslots;
+  hipEvent_t ev = nullptr;
+  DP_TRY(timing_begin(c, &ev));
   DP_HIP(c, launch_hop(a, c->stream));
+  if (c->timing) {
+    static const char* epi_names[] = {"hop", "inv", "diag", "sub", "invsub"};
+    double bytes, flops;
+    hop_cost(c, prec, epi, red, active_slots(c, mask, nslots), &bytes, &flops);
+    std::string name = std::string("hop_") + prec_name(prec) + "_" + epi_names[epi] + (dag ? "_dag" : "");
+    DP_TRY(timing_end(c, ev, name, bytes, flops));
+  }
   return DP_OK;
 }
 
@@ -324,7 +424,16 @@ int blas(dp_ctx* c, int op, int nslots, int prec, const int* mask, std::initiali
     ++k;
   }
   a.red = reduce_ref(c, RED_NONE, fin);
+  hipEvent_t ev = nullptr;
+  DP_TRY(timing_begin(c, &ev));
   DP_HIP(c, launch_blas(op, a, c->stream));
+  if (c->timing) {
+    // vectors read + written per site and slot (FP64 ones counted at 8 bytes)
+    static const int nvec[] = {1, 2, 5, 4, 3, 7, 6, 3, 2, 3, 3, 1, 2};
+    const double b = prec == F64 ? 8.0 : prec == F32 ? 4.0 : 2.0;
+    const double bytes = (double)c->g.Vh * active_slots(c, mask, nslots) * nvec[op] * 24 * b;
+    DP_TRY(timing_end(c, ev, std::string("blas_") + prec_name(prec) + "_" + std::to_string(op), bytes, 0.0));
+  }
   return DP_OK;
 }
 
@@ -528,6 +637,7 @@ int run_solve(dp_ctx* c, const double2* eta_dev, int n, const dp_params& P, doub
       }
   }
   DP_HIP(c, hipStreamSynchronize(c->stream));
+  DP_TRY(timing_harvest(c));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   for (int s = 0; s < n; ++s) {
     if (hs[s].status != DP_OK && rc == DP_OK) rc = hs[s].status;
@@ -781,6 +891,7 @@ int dp_apply(dp_ctx* c, const double* in, double* out, int flags) {
                                  c->stream));
   DP_HIP(c, hipMemcpyAsync(out, c->scratch_aos.p, bytes, hipMemcpyDeviceToHost, c->stream));
   DP_HIP(c, hipStreamSynchronize(c->stream));
+  DP_TRY(timing_harvest(c));
   return DP_OK;
 }
 
@@ -808,6 +919,38 @@ int dp_solve_dev(dp_ctx* c, const void* eta, int nrhs, const dp_params* p, void*
   DP_TRY(check_state(c));
   if (stream) DP_HIP(c, hipStreamSynchronize((hipStream_t)stream));
   return run_solve(c, static_cast<const double2*>(eta), nrhs, *p, static_cast<double2*>(S), cpp, info);
+}
+
+int dp_set_timing(dp_ctx* c, int enable) {
+  if (!c) return DP_ERR_INVALID_ARG;
+  DP_HIP(c, hipSetDevice(c->device));
+  DP_HIP(c, hipStreamSynchronize(c->stream));
+  DP_TRY(timing_harvest(c));
+  c->kstats.clear();
+  c->timing = enable != 0;
+  return DP_OK;
+}
+
+int dp_get_timing(dp_ctx* c, dp_kernel_stat* out, int max, int* count) {
+  if (!c || !count || max < 0 || (max > 0 && !out)) return fail(c, DP_ERR_INVALID_ARG, "bad argument");
+  DP_HIP(c, hipSetDevice(c->device));
+  DP_HIP(c, hipStreamSynchronize(c->stream));
+  DP_TRY(timing_harvest(c));
+  int n = 0;
+  for (const auto& kv : c->kstats) {
+    if (n < max) {
+      dp_kernel_stat& o = out[n];
+      std::memset(&o, 0, sizeof o);
+      std::strncpy(o.name, kv.first.c_str(), sizeof o.name - 1);
+      o.launches = kv.second.launches;
+      o.ms = kv.second.ms;
+      o.bytes = kv.second.bytes;
+      o.flops = kv.second.flops;
+    }
+    ++n;
+  }
+  *count = n;
+  return DP_OK;
 }
 
 long long dp_footprint_bytes(const int dims[4], int nrhs, int precision, int new_masses) {
