@@ -77,37 +77,39 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
     } else if constexpr (OP == OP_BICG_XR) {
       const SlotScalars& s = a.sc[slot];
       const z alpha{s.alpha[0], s.alpha[1]}, omega{s.omega[0], s.omega[1]};
+      z D[12], E[12];
+      // every load before the first store, so that they can all be in flight
       ld<PX>(a.v[0], slot, i, Vh, A);  // x
       ld<P>(a.v[1], slot, i, Vh, B);   // p
       ld<P>(a.v[2], slot, i, Vh, C);   // s
-#pragma unroll
-      for (int c = 0; c < 12; ++c) A[c] = A[c] + cmul(alpha, B[c]) + cmul(omega, C[c]);
-      st<PX>(a.v[0], slot, i, Vh, A);
-      ld<P>(a.v[4], slot, i, Vh, B);  // t
-#pragma unroll
-      for (int c = 0; c < 12; ++c) C[c] = C[c] - cmul(omega, B[c]);  // r
-      st<P>(a.v[3], slot, i, Vh, C);
-      ld<P>(a.v[5], slot, i, Vh, B);  // rh
+      ld<P>(a.v[4], slot, i, Vh, D);   // t
+      ld<P>(a.v[5], slot, i, Vh, E);   // rh
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        const z d = cjmul(B[c], C[c]);
+        A[c] = A[c] + cmul(alpha, B[c]) + cmul(omega, C[c]);
+        C[c] = C[c] - cmul(omega, D[c]);  // r
+        const z d = cjmul(E[c], C[c]);
         red[0] += d.x;
         red[1] += d.y;
       }
       red[2] = norm2(C);
+      st<PX>(a.v[0], slot, i, Vh, A);
+      st<P>(a.v[3], slot, i, Vh, C);
     } else if constexpr (OP == OP_CG_XR) {
       const double ca = a.sc[slot].cg_a;
+      z D[12];
       ld<PX>(a.v[0], slot, i, Vh, A);  // x
       ld<P>(a.v[1], slot, i, Vh, B);   // p
+      ld<P>(a.v[2], slot, i, Vh, C);   // r
+      ld<P>(a.v[3], slot, i, Vh, D);   // w
 #pragma unroll
-      for (int c = 0; c < 12; ++c) A[c] = A[c] + ca * B[c];
+      for (int c = 0; c < 12; ++c) {
+        A[c] = A[c] + ca * B[c];
+        C[c] = C[c] - ca * D[c];
+      }
+      red[0] = norm2(C);
       st<PX>(a.v[0], slot, i, Vh, A);
-      ld<P>(a.v[2], slot, i, Vh, B);  // r
-      ld<P>(a.v[3], slot, i, Vh, C);  // w
-#pragma unroll
-      for (int c = 0; c < 12; ++c) B[c] = B[c] - ca * C[c];
-      st<P>(a.v[2], slot, i, Vh, B);
-      red[0] = norm2(B);
+      st<P>(a.v[2], slot, i, Vh, C);
     } else if constexpr (OP == OP_CG_P) {
       const double cb = a.sc[slot].cg_b;
       ld<P>(a.v[0], slot, i, Vh, A);  // p

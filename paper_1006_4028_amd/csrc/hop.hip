@@ -19,7 +19,8 @@
 //   mu = k: h = u + s (i sigma_k) l,     lower = -s (i sigma_k) h
 // so only the two upper spins are multiplied by the link.
 //
-// One thread per output site and right-hand side; blockIdx.y is the slot.
+// One thread per output site and group of up to four right-hand sides
+// ("slots"); the links of the site are loaded once for the group.
 #include "dp_device.h"
 
 namespace dp {
@@ -102,10 +103,13 @@ __device__ __forceinline__ void link_dag_mul(const cx<R> (&u)[9], const Half<R>&
     }
 }
 
-template <int P, int MU>
-__device__ __forceinline__ void hop_dir(const HopArgs& a, int slot, int i, const int (&x)[4], typename Tr<P>::R cf,
-                                        typename Tr<P>::R cb, typename Tr<P>::R sg,
-                                        cx<typename Tr<P>::R> (&acc)[12]) {
+// One direction mu, both hops, for the active slots of this thread's group.
+// The link is loaded once and used for every slot.
+template <int P, int MU, int NS>
+__device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], const bool (&on)[NS], int i,
+                                        const int (&x)[4],
+                                        const typename Tr<P>::R (&cf)[NS], const typename Tr<P>::R (&cb)[NS],
+                                        typename Tr<P>::R sg, cx<typename Tr<P>::R> (&acc)[NS][12]) {
   using R = typename Tr<P>::R;
   const Geom& g = a.g;
   const int L = MU == 0 ? g.T : MU == 1 ? g.L1 : MU == 2 ? g.L2 : g.L3;
@@ -115,126 +119,182 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, int slot, int i, const
   // forward neighbour x + mu
   y[MU] = x[MU] + 1 == L ? 0 : x[MU] + 1;
   const int jf = eo_index(g, y[0], y[1], y[2], y[3]);
-  SpinorIO<P>::load(a.in, slot, jf, g.Vh, psi);
-  project<MU>(psi, sg, h);
   LinkIO<P>::load(a.U_out, MU, i, g.Vh, u);
-  link_mul(u, h, w);
-  accumulate<MU>(acc, w, sg, MU == 0 ? cf : R(1));
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    if (on[k]) {
+      SpinorIO<P>::load(a.in, sl[k], jf, g.Vh, psi);
+      project<MU>(psi, sg, h);
+      link_mul(u, h, w);
+      accumulate<MU>(acc[k], w, sg, MU == 0 ? cf[k] : R(1));
+    }
+  }
   // backward neighbour x - mu
   y[MU] = x[MU] == 0 ? L - 1 : x[MU] - 1;
   const int jb = eo_index(g, y[0], y[1], y[2], y[3]);
-  SpinorIO<P>::load(a.in, slot, jb, g.Vh, psi);
-  project<MU>(psi, -sg, h);
   LinkIO<P>::load(a.U_in, MU, jb, g.Vh, u);
-  link_dag_mul(u, h, w);
-  accumulate<MU>(acc, w, -sg, MU == 0 ? cb : R(1));
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    if (on[k]) {
+      SpinorIO<P>::load(a.in, sl[k], jb, g.Vh, psi);
+      project<MU>(psi, -sg, h);
+      link_dag_mul(u, h, w);
+      accumulate<MU>(acc[k], w, -sg, MU == 0 ? cb[k] : R(1));
+    }
+  }
 }
 
+// Epilogue and fused reduction terms for one slot.
 template <int P, int EPI, int RED>
+__device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<typename Tr<P>::R> (&acc)[12],
+                                         double (&red)[4]) {
+  using R = typename Tr<P>::R;
+  const Geom& g = a.g;
+  cx<R> out[12], xin[12], wv[12];
+  if constexpr (EPI == EPI_DIAG || EPI == EPI_SUB || EPI == EPI_INV_SUB) SpinorIO<P>::load(a.xin, slot, i, g.Vh, xin);
+  if constexpr (RED == RED_DOT_EXT) SpinorIO<P>::load(a.red.w, slot, i, g.Vh, wv);
+  if constexpr (EPI == EPI_HOP) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[c] = R(-0.5) * acc[c];
+  } else if constexpr (EPI == EPI_DIAG) {
+    HermBlock<R> B[2];
+    CloverIO<P>::load(a.clov.data, a.clov.scale, i, g.Vh, B);
+    const R m4 = (R)a.slots.m4[slot];
+    herm_apply(B[0], m4, &xin[0], &out[0]);
+    herm_apply(B[1], m4, &xin[6], &out[6]);
+    const R hs = (R)(-0.5 * a.sign);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[c] = out[c] + hs * acc[c];
+  } else if constexpr (EPI == EPI_SUB) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[c] = xin[c] + R(0.5) * acc[c];
+  } else {  // EPI_INV, EPI_INV_SUB
+    cx<R> t[12];
+    if constexpr (EPI == EPI_INV_SUB) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) t[c] = xin[c] + R(0.5) * acc[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) t[c] = R(-0.5) * acc[c];
+    }
+    HermBlock<R> B[2];
+    const float* sc = a.slots.ainv_scale ? a.slots.ainv_scale[slot] : nullptr;
+    CloverIO<P>::load(a.slots.ainv[slot], sc, i, g.Vh, B);
+    herm_apply(B[0], R(0), &t[0], &out[0]);
+    herm_apply(B[1], R(0), &t[6], &out[6]);
+  }
+  SpinorIO<P>::store(a.out, slot, i, g.Vh, out);
+  if constexpr (RED == RED_DOT_EXT) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      red[0] += (double)wv[c].x * (double)out[c].x + (double)wv[c].y * (double)out[c].y;
+      red[1] += (double)wv[c].x * (double)out[c].y - (double)wv[c].y * (double)out[c].x;
+    }
+  } else if constexpr (RED == RED_TS) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      red[0] += (double)out[c].x * (double)xin[c].x + (double)out[c].y * (double)xin[c].y;
+      red[1] += (double)out[c].x * (double)xin[c].y - (double)out[c].y * (double)xin[c].x;
+      red[2] += (double)out[c].x * (double)out[c].x + (double)out[c].y * (double)out[c].y;
+    }
+  } else if constexpr (RED == RED_NORM) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) red[0] += (double)out[c].x * (double)out[c].x + (double)out[c].y * (double)out[c].y;
+  }
+}
+
+// Grid: one block per (tile of kBlock sites, group of NS slots); the blocks
+// of each XCD cover a contiguous range of tiles with all slot groups of a
+// tile next to each other, so the groups of a tile share its links in L2.
+template <int P, int EPI, int RED, int NS>
 __global__ void __launch_bounds__(kBlock) hop_kernel(HopArgs a) {
   using R = typename Tr<P>::R;
   const Geom& g = a.g;
-  const int slot = blockIdx.y;
-  if (a.slots.mask && !a.slots.mask[slot]) return;  // uniform over the slot's blocks
-  const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  double red[4] = {0.0, 0.0, 0.0, 0.0};
+  const int ngroups = (a.nslots + NS - 1) / NS;
+  const int f = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = f / ngroups, grp = f - tile * ngroups;
+  const int ntiles = gridDim.x / ngroups;
+  // active slots of the group (uniform over the block)
+  int sl[NS];
+  bool on[NS];
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    sl[k] = grp * NS + k;
+    on[k] = sl[k] < a.nslots && (!a.slots.mask || a.slots.mask[sl[k]]);
+    if (!on[k]) sl[k] = 0;
+    any = any || on[k];
+  }
+  if (!any) return;
+  const int i = tile * kBlock + threadIdx.x;
+  double red[NS][4];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) red[k][0] = red[k][1] = red[k][2] = red[k][3] = 0.0;
   if (i < g.Vh) {
     int x[4];
     eo_coords(g, a.p, i, x[0], x[1], x[2], x[3]);
-    const double* rt = a.slots.ratio + (long)slot * 4 * g.T;
-    const R cf = (R)(a.dag ? rt[2 * g.T + x[0]] : rt[x[0]]);
-    const R cb = (R)(a.dag ? rt[3 * g.T + x[0]] : rt[g.T + x[0]]);
+    R cf[NS], cb[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const double* rt = a.slots.ratio + (long)sl[k] * 4 * g.T;
+      cf[k] = (R)(a.dag ? rt[2 * g.T + x[0]] : rt[x[0]]);
+      cb[k] = (R)(a.dag ? rt[3 * g.T + x[0]] : rt[g.T + x[0]]);
+    }
     const R sg = a.dag ? R(-1) : R(1);
-    cx<R> acc[12];
+    cx<R> acc[NS][12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = cx<R>{R(0), R(0)};
-    hop_dir<P, 0>(a, slot, i, x, cf, cb, sg, acc);
-    hop_dir<P, 1>(a, slot, i, x, cf, cb, sg, acc);
-    hop_dir<P, 2>(a, slot, i, x, cf, cb, sg, acc);
-    hop_dir<P, 3>(a, slot, i, x, cf, cb, sg, acc);
-
-    cx<R> out[12], xin[12];
-    if constexpr (EPI == EPI_HOP) {
+    for (int k = 0; k < NS; ++k)
 #pragma unroll
-      for (int c = 0; c < 12; ++c) out[c] = R(-0.5) * acc[c];
-    } else if constexpr (EPI == EPI_DIAG) {
-      SpinorIO<P>::load(a.xin, slot, i, g.Vh, xin);
-      HermBlock<R> B[2];
-      CloverIO<P>::load(a.clov.data, a.clov.scale, i, g.Vh, B);
-      const R m4 = (R)a.slots.m4[slot];
-      herm_apply(B[0], m4, &xin[0], &out[0]);
-      herm_apply(B[1], m4, &xin[6], &out[6]);
-      const R hs = (R)(-0.5 * a.sign);
+      for (int c = 0; c < 12; ++c) acc[k][c] = cx<R>{R(0), R(0)};
+    hop_dir<P, 0, NS>(a, sl, on, i, x, cf, cb, sg, acc);
+    hop_dir<P, 1, NS>(a, sl, on, i, x, cf, cb, sg, acc);
+    hop_dir<P, 2, NS>(a, sl, on, i, x, cf, cb, sg, acc);
+    hop_dir<P, 3, NS>(a, sl, on, i, x, cf, cb, sg, acc);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) out[c] = out[c] + hs * acc[c];
-    } else if constexpr (EPI == EPI_SUB) {
-      SpinorIO<P>::load(a.xin, slot, i, g.Vh, xin);
-#pragma unroll
-      for (int c = 0; c < 12; ++c) out[c] = xin[c] + R(0.5) * acc[c];
-    } else {  // EPI_INV, EPI_INV_SUB
-      cx<R> t[12];
-      if constexpr (EPI == EPI_INV_SUB) {
-        SpinorIO<P>::load(a.xin, slot, i, g.Vh, xin);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) t[c] = xin[c] + R(0.5) * acc[c];
-      } else {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) t[c] = R(-0.5) * acc[c];
-      }
-      HermBlock<R> B[2];
-      const float* sc = a.slots.ainv_scale ? a.slots.ainv_scale[slot] : nullptr;
-      CloverIO<P>::load(a.slots.ainv[slot], sc, i, g.Vh, B);
-      herm_apply(B[0], R(0), &t[0], &out[0]);
-      herm_apply(B[1], R(0), &t[6], &out[6]);
-    }
-    SpinorIO<P>::store(a.out, slot, i, g.Vh, out);
-
-    if constexpr (RED == RED_DOT_EXT) {
-      cx<R> w[12];
-      SpinorIO<P>::load(a.red.w, slot, i, g.Vh, w);
-#pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        red[0] += (double)w[c].x * (double)out[c].x + (double)w[c].y * (double)out[c].y;
-        red[1] += (double)w[c].x * (double)out[c].y - (double)w[c].y * (double)out[c].x;
-      }
-    } else if constexpr (RED == RED_TS) {
-#pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        red[0] += (double)out[c].x * (double)xin[c].x + (double)out[c].y * (double)xin[c].y;
-        red[1] += (double)out[c].x * (double)xin[c].y - (double)out[c].y * (double)xin[c].x;
-        red[2] += (double)out[c].x * (double)out[c].x + (double)out[c].y * (double)out[c].y;
-      }
-    } else if constexpr (RED == RED_NORM) {
-#pragma unroll
-      for (int c = 0; c < 12; ++c) red[0] += (double)out[c].x * (double)out[c].x + (double)out[c].y * (double)out[c].y;
-    }
+    for (int k = 0; k < NS; ++k)
+      if (on[k]) epilogue<P, EPI, RED>(a, sl[k], i, acc[k], red[k]);
   }
   if constexpr (RED != RED_NONE) {
-    const int nv = RED == RED_DOT_EXT ? 2 : RED == RED_TS ? 3 : 1;
-    block_reduce_finalize(a.red, nv, red, slot, blockIdx.x, gridDim.x);
+    constexpr int nv = RED == RED_DOT_EXT ? 2 : RED == RED_TS ? 3 : 1;
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+      if (on[k]) block_reduce_finalize(a.red, nv, red[k], sl[k], tile, ntiles);
   }
 }
 
-template <int P, int EPI>
-hipError_t launch_red(const HopArgs& a, dim3 grid, hipStream_t st) {
-  switch (a.red.red) {
-    case RED_NONE: hipLaunchKernelGGL((hop_kernel<P, EPI, RED_NONE>), grid, dim3(kBlock), 0, st, a); break;
-    case RED_DOT_EXT: hipLaunchKernelGGL((hop_kernel<P, EPI, RED_DOT_EXT>), grid, dim3(kBlock), 0, st, a); break;
-    case RED_TS: hipLaunchKernelGGL((hop_kernel<P, EPI, RED_TS>), grid, dim3(kBlock), 0, st, a); break;
-    case RED_NORM: hipLaunchKernelGGL((hop_kernel<P, EPI, RED_NORM>), grid, dim3(kBlock), 0, st, a); break;
-    default: return hipErrorInvalidValue;
+template <int P, int EPI, int RED>
+hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st) {
+  // slots per thread: four in the inner precisions; in FP64 the clover
+  // epilogue already fills the register file with one
+  int ns = a.nslots >= 4 ? 4 : a.nslots >= 2 ? 2 : 1;
+  if (P == F64) ns = (EPI == EPI_DIAG || a.nslots < 2) ? 1 : 2;
+  const int ngroups = (a.nslots + ns - 1) / ns;
+  const dim3 grid(ntiles * ngroups);
+  switch (ns) {
+    case 4: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 4>), grid, dim3(kBlock), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 2>), grid, dim3(kBlock), 0, st, a); break;
+    default: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 1>), grid, dim3(kBlock), 0, st, a); break;
   }
   return hipGetLastError();
 }
 
 template <int P>
-hipError_t launch_epi(const HopArgs& a, dim3 grid, hipStream_t st) {
+hipError_t launch_epi(const HopArgs& a, int ntiles, hipStream_t st) {
+  // fused reductions are only used with the even-site Schur epilogue
+  if (a.red.red != RED_NONE && a.epi != EPI_DIAG) return hipErrorInvalidValue;
   switch (a.epi) {
-    case EPI_HOP: return launch_red<P, EPI_HOP>(a, grid, st);
-    case EPI_INV: return launch_red<P, EPI_INV>(a, grid, st);
-    case EPI_DIAG: return launch_red<P, EPI_DIAG>(a, grid, st);
-    case EPI_SUB: return launch_red<P, EPI_SUB>(a, grid, st);
-    case EPI_INV_SUB: return launch_red<P, EPI_INV_SUB>(a, grid, st);
+    case EPI_HOP: return launch_ns<P, EPI_HOP, RED_NONE>(a, ntiles, st);
+    case EPI_INV: return launch_ns<P, EPI_INV, RED_NONE>(a, ntiles, st);
+    case EPI_SUB: return launch_ns<P, EPI_SUB, RED_NONE>(a, ntiles, st);
+    case EPI_INV_SUB: return launch_ns<P, EPI_INV_SUB, RED_NONE>(a, ntiles, st);
+    case EPI_DIAG:
+      switch (a.red.red) {
+        case RED_NONE: return launch_ns<P, EPI_DIAG, RED_NONE>(a, ntiles, st);
+        case RED_DOT_EXT: return launch_ns<P, EPI_DIAG, RED_DOT_EXT>(a, ntiles, st);
+        case RED_TS: return launch_ns<P, EPI_DIAG, RED_TS>(a, ntiles, st);
+        case RED_NORM: return launch_ns<P, EPI_DIAG, RED_NORM>(a, ntiles, st);
+        default: return hipErrorInvalidValue;
+      }
     default: return hipErrorInvalidValue;
   }
 }
@@ -246,11 +306,11 @@ int reduction_blocks(const Geom& g) { return (g.Vh + kBlock - 1) / kBlock; }
 hipError_t launch_hop(const HopArgs& a, hipStream_t st) {
   if (a.nslots <= 0 || a.g.Vh <= 0) return hipErrorInvalidValue;
   if (a.in.prec != a.out.prec || a.link_prec != a.in.prec) return hipErrorInvalidValue;
-  const dim3 grid(reduction_blocks(a.g), a.nslots);
+  const int ntiles = reduction_blocks(a.g);
   switch (a.in.prec) {
-    case F64: return launch_epi<F64>(a, grid, st);
-    case F32: return launch_epi<F32>(a, grid, st);
-    case F16: return launch_epi<F16>(a, grid, st);
+    case F64: return launch_epi<F64>(a, ntiles, st);
+    case F32: return launch_epi<F32>(a, ntiles, st);
+    case F16: return launch_epi<F16>(a, ntiles, st);
     default: return hipErrorInvalidValue;
   }
 }
