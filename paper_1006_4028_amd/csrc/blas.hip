@@ -1,6 +1,7 @@
 // Fused vector kernels of the Krylov solvers (BiCGStab of van der Vorst 1992
 // and CG on the normal equations) over the even sites of every active slot,
-// with their global reductions fused in (see block_reduce_finalize).  The
+// with their global reductions fused in (block partials, then a finalise
+// kernel on the same stream; see block_reduce_store).  The
 // arithmetic is FP64 whatever the storage precision; scalars come from the
 // slot's device-resident SlotScalars.
 #include "dp_device.h"
@@ -145,7 +146,30 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
       red[0] = norm2(B);
     }
   }
-  if (nv > 0 && a.red.fin != FIN_NONE) block_reduce_finalize(a.red, nv, red, slot, blockIdx.x, gridDim.x);
+  if (nv > 0 && a.red.fin != FIN_NONE) block_reduce_store(a.red, nv, red, slot, blockIdx.x, gridDim.x);
+}
+
+// one block per slot: fold the block partials in block order, then finalise
+__global__ void __launch_bounds__(kBlock) finalize_kernel(ReduceRef red, int nv, int nblocks, const int* mask) {
+  const int slot = blockIdx.x;
+  if (mask && !mask[slot]) return;
+  __shared__ double lds[4][kBlock / 64];
+  const double* part = red.partials + (long)slot * nblocks * 4;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += kBlock)
+    for (int k = 0; k < nv; ++k) acc[k] += part[(long)b * 4 + k];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < nv; ++k) {
+    const double w = wave_sum(acc[k]);
+    if (lane == 0) lds[k][wid] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < nv; ++k)
+      for (int w = 0; w < kBlock / 64; ++w) s[k] += lds[k][w];
+    run_finaliser(red, slot, s);
+  }
 }
 
 template <int P>
@@ -174,15 +198,27 @@ hipError_t launch_p(int op, const BlasArgs& a, dim3 grid, hipStream_t st) {
 
 }  // namespace
 
+hipError_t launch_finalize(const ReduceRef& red, int nv, int nblocks, int nslots, const int* mask, hipStream_t st) {
+  if (nslots <= 0 || nv < 1 || nv > 4) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(finalize_kernel, dim3(nslots), dim3(kBlock), 0, st, red, nv, nblocks, mask);
+  return hipGetLastError();
+}
+
 hipError_t launch_blas(int op, const BlasArgs& a, hipStream_t st) {
   if (a.nslots <= 0 || a.g.Vh <= 0) return hipErrorInvalidValue;
-  const dim3 grid(reduction_blocks(a.g), a.nslots);
+  const int nb = reduction_blocks(a.g);
+  const dim3 grid(nb, a.nslots);
+  hipError_t e;
   switch (a.prec) {
-    case F64: return launch_p<F64>(op, a, grid, st);
-    case F32: return launch_p<F32>(op, a, grid, st);
-    case F16: return launch_p<F16>(op, a, grid, st);
+    case F64: e = launch_p<F64>(op, a, grid, st); break;
+    case F32: e = launch_p<F32>(op, a, grid, st); break;
+    case F16: e = launch_p<F16>(op, a, grid, st); break;
     default: return hipErrorInvalidValue;
   }
+  if (e != hipSuccess || a.red.fin == FIN_NONE) return e;
+  const int nv = op == OP_BICG_XR ? 3 : (op == OP_BICG_INIT || op == OP_CG_XR || op == OP_SUB64 || op == OP_NORM) ? 1 : 0;
+  if (nv == 0) return hipErrorInvalidValue;
+  return launch_finalize(a.red, nv, nb, a.nslots, a.mask, st);
 }
 
 }  // namespace dp

@@ -89,8 +89,9 @@ enum Epi {
   EPI_INV_SUB = 4,  // out = A^-1 (xin - H in)
 };
 
-// Reductions fused into a kernel's epilogue; results land in per-slot partials
-// and the last block of each slot folds them in a fixed order and runs a finaliser.
+// Reductions fused into a kernel's epilogue; results land in per-slot block
+// partials, and a finalise kernel on the same stream folds them in a fixed
+// order and runs a finaliser.
 enum Red {
   RED_NONE = 0,
   RED_DOT_EXT = 1,  // <w, out>      (w = extra vector, e.g. the shadow residual)
@@ -116,7 +117,6 @@ struct ReduceRef {
   int fin = FIN_NONE;
   SpinorRef w;               // RED_DOT_EXT partner
   double* partials = nullptr;   // [nslots][nblocks][4]
-  unsigned* counters = nullptr; // [nslots], zero between launches
   SlotScalars* sc = nullptr;    // [nslots]
   double* out_sums = nullptr;   // FIN_STORE: [nslots][4]
 };
@@ -208,6 +208,11 @@ enum BlasOp {
 };
 
 hipError_t launch_blas(int op, const BlasArgs& a, hipStream_t stream);
+
+// Fold the per-block partials of every active slot (mask may be null) in block
+// order and run red.fin; nv values per block, nblocks blocks per slot.
+hipError_t launch_finalize(const ReduceRef& red, int nv, int nblocks, int nslots, const int* mask,
+                           hipStream_t stream);
 
 // Number of blocks a reduction launch uses for a given geometry (so that the
 // caller can size the partials buffer).

@@ -314,13 +314,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ double ld_agent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // complex a / b
 __device__ __forceinline__ void cdiv(const double* a, const double* b, double* out) {
   const double den = b[0] * b[0] + b[1] * b[1];
@@ -404,51 +397,29 @@ __device__ inline void run_finaliser(const ReduceRef& red, int slot, const doubl
   }
 }
 
-// Sum nv values over the block (fixed tree), write the block partial of the
-// slot, and let the last block of the slot fold all partials in block order
-// and run the finaliser.  Deterministic for a fixed launch shape, and a slot's
-// result depends only on that slot's data.  Every thread of the block must
+// Sum nv values over the block (fixed tree) and store the block's partial
+// for the slot.  A finalise kernel launched next on the same stream folds the
+// partials in block order (deterministic for a fixed launch shape; a slot's
+// result depends only on that slot's data).  Every thread of the block must
 // call this (no early return before it).
-__device__ inline void block_reduce_finalize(const ReduceRef& red, int nv, double (&v)[4], int slot, int block,
-                                             int nblocks) {
+__device__ inline void block_reduce_store(const ReduceRef& red, int nv, double (&v)[4], int slot, int block,
+                                          int nblocks) {
   __shared__ double lds[4][kBlock / 64];
-  __shared__ int is_last;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int k = 0; k < nv; ++k) {
     const double w = wave_sum(v[k]);
     if (lane == 0) lds[k][wid] = w;
   }
   __syncthreads();
-  double* part = red.partials + (long)slot * nblocks * 4;
   if (threadIdx.x == 0) {
+    double* part = red.partials + ((long)slot * nblocks + block) * 4;
     for (int k = 0; k < nv; ++k) {
       double t = 0.0;
       for (int w = 0; w < kBlock / 64; ++w) t += lds[k][w];
-      st_agent(part + (long)block * 4 + k, t);
+      part[k] = t;
     }
-    __threadfence();
-    const unsigned prev = atomicAdd(&red.counters[slot], 1u);
-    is_last = (prev == (unsigned)(nblocks - 1));
   }
   __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nblocks; b += kBlock)
-    for (int k = 0; k < nv; ++k) acc[k] += ld_agent(part + (long)b * 4 + k);
-  __syncthreads();
-  for (int k = 0; k < nv; ++k) {
-    const double w = wave_sum(acc[k]);
-    if (lane == 0) lds[k][wid] = w;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < nv; ++k)
-      for (int w = 0; w < kBlock / 64; ++w) s[k] += lds[k][w];
-    run_finaliser(red, slot, s);
-    atomicExch(&red.counters[slot], 0u);
-  }
 }
 
 }  // namespace dp

@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(kBlock) hop_kernel(HopArgs a) {
     constexpr int nv = RED == RED_DOT_EXT ? 2 : RED == RED_TS ? 3 : 1;
 #pragma unroll
     for (int k = 0; k < NS; ++k)
-      if (on[k]) block_reduce_finalize(a.red, nv, red[k], sl[k], tile, ntiles);
+      if (on[k]) block_reduce_store(a.red, nv, red[k], sl[k], tile, ntiles);
   }
 }
 
@@ -275,7 +275,10 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st) {
     case 2: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 2>), grid, dim3(kBlock), 0, st, a); break;
     default: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 1>), grid, dim3(kBlock), 0, st, a); break;
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || RED == RED_NONE) return e;
+  constexpr int nv = RED == RED_DOT_EXT ? 2 : RED == RED_TS ? 3 : 1;
+  return launch_finalize(a.red, nv, ntiles, a.nslots, a.slots.mask, st);
 }
 
 template <int P>

@@ -98,7 +98,7 @@ struct Workspace {
   // inner precision (x in FP32 when the inner precision is FP16)
   Field r, rh, p, v, s, t, x, to;
   // per-slot device tables
-  DevBuf ratio, m4, mask_all, mask_inner, mask_outer, ainv_ptr[3], ainv_scale_ptr, sc, partials, counters, out_sums,
+  DevBuf ratio, m4, mask_all, mask_inner, mask_outer, ainv_ptr[3], ainv_scale_ptr, sc, partials, out_sums,
       slot_scale, x0src, alpha, cpp, sp_aos;
   HostBuf h_sc, h_sums, h_mask, h_scale;
 };

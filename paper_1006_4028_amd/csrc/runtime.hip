@@ -204,8 +204,6 @@ int ensure_ws(dp_ctx* c, int nslots, int prec) {
     DP_HIP(c, w.ainv_scale_ptr.reserve(sizeof(float*) * n));
     DP_HIP(c, w.sc.reserve(sizeof(SlotScalars) * n));
     DP_HIP(c, w.partials.reserve(sizeof(double) * 4 * nb * n));
-    DP_HIP(c, w.counters.reserve(sizeof(unsigned) * n));
-    DP_HIP(c, hipMemsetAsync(w.counters.p, 0, sizeof(unsigned) * n, c->stream));
     DP_HIP(c, w.out_sums.reserve(sizeof(double) * 4 * n));
     DP_HIP(c, w.slot_scale.reserve(sizeof(double) * n));
     DP_HIP(c, w.x0src.reserve(sizeof(int) * n));
@@ -287,7 +285,6 @@ ReduceRef reduce_ref(dp_ctx* c, int red, int fin) {
   r.red = red;
   r.fin = fin;
   r.partials = w.partials.as<double>();
-  r.counters = w.counters.as<unsigned>();
   r.sc = w.sc.as<SlotScalars>();
   r.out_sums = w.out_sums.as<double>();
   return r;
