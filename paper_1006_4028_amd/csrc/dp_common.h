@@ -214,9 +214,10 @@ hipError_t launch_blas(int op, const BlasArgs& a, hipStream_t stream);
 hipError_t launch_finalize(const ReduceRef& red, int nv, int nblocks, int nslots, const int* mask,
                            hipStream_t stream);
 
-// Number of blocks a reduction launch uses for a given geometry (so that the
-// caller can size the partials buffer).
+// Number of blocks a BLAS launch (reduction_blocks) and a hop launch
+// (hop_blocks) use for a given geometry, to size the partials buffer.
 int reduction_blocks(const Geom& g);
+int hop_blocks(const Geom& g);
 constexpr int kBlock = 256;
 
 }  // namespace dp

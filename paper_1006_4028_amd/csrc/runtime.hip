@@ -17,6 +17,7 @@
 //     inner mask at once (links are shared through the caches).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -194,7 +195,7 @@ int ensure_ws(dp_ctx* c, int nslots, int prec) {
     Field* fin[] = {&w.r, &w.rh, &w.p, &w.v, &w.s, &w.t, &w.to};
     for (Field* f : fin) DP_HIP(c, f->alloc(g, prec, n));
     DP_HIP(c, w.x.alloc(g, px, n));
-    const int nb = reduction_blocks(g);
+    const int nb = std::max(reduction_blocks(g), hop_blocks(g));
     DP_HIP(c, w.ratio.reserve(sizeof(double) * 4 * g.T * n));
     DP_HIP(c, w.m4.reserve(sizeof(double) * n));
     DP_HIP(c, w.mask_all.reserve(sizeof(int) * n));
