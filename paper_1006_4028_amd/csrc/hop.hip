@@ -19,8 +19,8 @@
 //   mu = k: h = u + s (i sigma_k) l,     lower = -s (i sigma_k) h
 // so only the two upper spins are multiplied by the link.
 //
-// One thread per output site; it runs the stencil for up to four
-// right-hand sides ("slots") at a time with the links loaded once.
+// One thread per output site and group of up to four right-hand sides
+// ("slots"); the links of the site are loaded once for the group.
 #include "dp_device.h"
 
 namespace dp {
@@ -203,81 +203,73 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
   }
 }
 
-// Grid: one block per (4 consecutive timeslices) x (64 consecutive spatial
-// sites of one parity); wave w of the block takes timeslice 4t + w, so the
-// x0 +- 1 neighbours of a wave are the sites of its sibling waves and come
-// from the CU's caches.  The blocks of each XCD cover a contiguous range of
-// such tiles, spatial tiles fastest.  Every block loops over the slot groups
-// (NS slots per thread at a time), so a tile's links and clover blocks are
-// fetched once from HBM for all right-hand sides.
+// Grid: one block per (tile of kBlock sites, group of NS slots); the blocks
+// of each XCD cover a contiguous range of tiles with all slot groups of a
+// tile next to each other, so the groups of a tile share its links in L2.
 template <int P, int EPI, int RED, int NS>
 __global__ void __launch_bounds__(kBlock) hop_kernel(HopArgs a) {
   using R = typename Tr<P>::R;
   const Geom& g = a.g;
-  const int nsp = (g.Vsh + 63) >> 6;
-  const int f = xcd_tile(blockIdx.x, gridDim.x);
-  const int tt = f / nsp, ct = f - tt * nsp;
-  const int x0w = 4 * tt + (threadIdx.x >> 6);
-  const int sp = 64 * ct + (threadIdx.x & 63);
-  const bool valid = x0w < g.T && sp < g.Vsh;
-  const int i = valid ? x0w * g.Vsh + sp : 0;
-  int x[4] = {0, 0, 0, 0};
-  if (valid) eo_coords(g, a.p, i, x[0], x[1], x[2], x[3]);
-  const R sg = a.dag ? R(-1) : R(1);
   const int ngroups = (a.nslots + NS - 1) / NS;
-  for (int grp = 0; grp < ngroups; ++grp) {
-    // active slots of the group (uniform over the block)
-    int sl[NS];
-    bool on[NS];
-    bool any = false;
+  const int f = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = f / ngroups, grp = f - tile * ngroups;
+  const int ntiles = gridDim.x / ngroups;
+  // active slots of the group (uniform over the block)
+  int sl[NS];
+  bool on[NS];
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    sl[k] = grp * NS + k;
+    on[k] = sl[k] < a.nslots && (!a.slots.mask || a.slots.mask[sl[k]]);
+    if (!on[k]) sl[k] = 0;
+    any = any || on[k];
+  }
+  if (!any) return;
+  const int i = tile * kBlock + threadIdx.x;
+  double red[NS][4];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) red[k][0] = red[k][1] = red[k][2] = red[k][3] = 0.0;
+  if (i < g.Vh) {
+    int x[4];
+    eo_coords(g, a.p, i, x[0], x[1], x[2], x[3]);
+    R cf[NS], cb[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      sl[k] = grp * NS + k;
-      on[k] = sl[k] < a.nslots && (!a.slots.mask || a.slots.mask[sl[k]]);
-      if (!on[k]) sl[k] = 0;
-      any = any || on[k];
+      const double* rt = a.slots.ratio + (long)sl[k] * 4 * g.T;
+      cf[k] = (R)(a.dag ? rt[2 * g.T + x[0]] : rt[x[0]]);
+      cb[k] = (R)(a.dag ? rt[3 * g.T + x[0]] : rt[g.T + x[0]]);
     }
-    if (!any) continue;
-    double red[NS][4];
+    const R sg = a.dag ? R(-1) : R(1);
+    cx<R> acc[NS][12];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) red[k][0] = red[k][1] = red[k][2] = red[k][3] = 0.0;
-    if (valid) {
-      R cf[NS], cb[NS];
+    for (int k = 0; k < NS; ++k)
 #pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        const double* rt = a.slots.ratio + (long)sl[k] * 4 * g.T;
-        cf[k] = (R)(a.dag ? rt[2 * g.T + x[0]] : rt[x[0]]);
-        cb[k] = (R)(a.dag ? rt[3 * g.T + x[0]] : rt[g.T + x[0]]);
-      }
-      cx<R> acc[NS][12];
+      for (int c = 0; c < 12; ++c) acc[k][c] = cx<R>{R(0), R(0)};
+    hop_dir<P, 0, NS>(a, sl, on, i, x, cf, cb, sg, acc);
+    hop_dir<P, 1, NS>(a, sl, on, i, x, cf, cb, sg, acc);
+    hop_dir<P, 2, NS>(a, sl, on, i, x, cf, cb, sg, acc);
+    hop_dir<P, 3, NS>(a, sl, on, i, x, cf, cb, sg, acc);
 #pragma unroll
-      for (int k = 0; k < NS; ++k)
+    for (int k = 0; k < NS; ++k)
+      if (on[k]) epilogue<P, EPI, RED>(a, sl[k], i, acc[k], red[k]);
+  }
+  if constexpr (RED != RED_NONE) {
+    constexpr int nv = RED == RED_DOT_EXT ? 2 : RED == RED_TS ? 3 : 1;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) acc[k][c] = cx<R>{R(0), R(0)};
-      hop_dir<P, 0, NS>(a, sl, on, i, x, cf, cb, sg, acc);
-      hop_dir<P, 1, NS>(a, sl, on, i, x, cf, cb, sg, acc);
-      hop_dir<P, 2, NS>(a, sl, on, i, x, cf, cb, sg, acc);
-      hop_dir<P, 3, NS>(a, sl, on, i, x, cf, cb, sg, acc);
-#pragma unroll
-      for (int k = 0; k < NS; ++k)
-        if (on[k]) epilogue<P, EPI, RED>(a, sl[k], i, acc[k], red[k]);
-    }
-    if constexpr (RED != RED_NONE) {
-      constexpr int nv = RED == RED_DOT_EXT ? 2 : RED == RED_TS ? 3 : 1;
-#pragma unroll
-      for (int k = 0; k < NS; ++k)
-        if (on[k]) block_reduce_store(a.red, nv, red[k], sl[k], f, gridDim.x);
-    }
+    for (int k = 0; k < NS; ++k)
+      if (on[k]) block_reduce_store(a.red, nv, red[k], sl[k], tile, ntiles);
   }
 }
 
 template <int P, int EPI, int RED>
-hipError_t launch_ns(const HopArgs& a, int nblocks, hipStream_t st) {
-  // slots per thread and round: four in the inner precisions; in FP64 the
-  // clover epilogue already fills the register file with one
+hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st) {
+  // slots per thread: four in the inner precisions; in FP64 the clover
+  // epilogue already fills the register file with one
   int ns = a.nslots >= 4 ? 4 : a.nslots >= 2 ? 2 : 1;
   if (P == F64) ns = (EPI == EPI_DIAG || a.nslots < 2) ? 1 : 2;
-  const dim3 grid(nblocks);
+  const int ngroups = (a.nslots + ns - 1) / ns;
+  const dim3 grid(ntiles * ngroups);
   switch (ns) {
     case 4: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 4>), grid, dim3(kBlock), 0, st, a); break;
     case 2: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 2>), grid, dim3(kBlock), 0, st, a); break;
@@ -286,11 +278,11 @@ hipError_t launch_ns(const HopArgs& a, int nblocks, hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || RED == RED_NONE) return e;
   constexpr int nv = RED == RED_DOT_EXT ? 2 : RED == RED_TS ? 3 : 1;
-  return launch_finalize(a.red, nv, nblocks, a.nslots, a.slots.mask, st);
+  return launch_finalize(a.red, nv, ntiles, a.nslots, a.slots.mask, st);
 }
 
 template <int P>
-hipError_t launch_epi(const HopArgs& a, int ntiles, hipStream_t st) {  // ntiles: blocks of the grid
+hipError_t launch_epi(const HopArgs& a, int ntiles, hipStream_t st) {
   // fused reductions are only used with the even-site Schur epilogue
   if (a.red.red != RED_NONE && a.epi != EPI_DIAG) return hipErrorInvalidValue;
   switch (a.epi) {
@@ -314,12 +306,12 @@ hipError_t launch_epi(const HopArgs& a, int ntiles, hipStream_t st) {  // ntiles
 
 int reduction_blocks(const Geom& g) { return (g.Vh + kBlock - 1) / kBlock; }
 
-int hop_blocks(const Geom& g) { return ((g.T + 3) / 4) * ((g.Vsh + 63) / 64); }
+int hop_blocks(const Geom& g) { return reduction_blocks(g); }
 
 hipError_t launch_hop(const HopArgs& a, hipStream_t st) {
   if (a.nslots <= 0 || a.g.Vh <= 0) return hipErrorInvalidValue;
   if (a.in.prec != a.out.prec || a.link_prec != a.in.prec) return hipErrorInvalidValue;
-  const int ntiles = hop_blocks(a.g);
+  const int ntiles = reduction_blocks(a.g);
   switch (a.in.prec) {
     case F64: return launch_epi<F64>(a, ntiles, st);
     case F32: return launch_epi<F32>(a, ntiles, st);
