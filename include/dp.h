@@ -59,6 +59,7 @@ extern "C" {
 #define DP_ERR_BREAKDOWN (-5)
 #define DP_ERR_NONFINITE (-6)
 #define DP_ERR_BAD_STATE (-7)
+#define DP_ERR_FULL (-8) /* a batch has no free slot for the request */
 
 /* inner precision of a solve */
 #define DP_PREC_F64 0 /* FP64 throughout */
@@ -79,6 +80,7 @@ extern "C" {
 #define DP_APPLY_F16 32  /* compute in the FP16-storage kernels */
 
 typedef struct dp_ctx dp_ctx;
+typedef struct dp_batch dp_batch;
 
 typedef struct {
   double r;        /* target relative residual of the preconditioned system (> 0) */
@@ -166,6 +168,44 @@ typedef struct {
 } dp_kernel_stat;
 int dp_set_timing(dp_ctx* ctx, int enable);
 int dp_get_timing(dp_ctx* ctx, dp_kernel_stat* out, int max, int* count);
+
+/* ------------------------------------------------------------------ batches
+ * A batch is a fixed set of nslots slots on one ctx, each solving one
+ * right-hand side with its own mass, alpha profile, residue and source
+ * timeslice.  Requests enter (dp_batch_admit) and leave (dp_batch_harvest)
+ * while others run: every dp_batch_step runs k Krylov iterations for all
+ * running slots at once (the hop kernel shares the links among them), then
+ * the FP64 outer step for the slots whose inner solve ended.  A slot's
+ * arithmetic does not depend on the other slots, so a result is the same
+ * alone and in any mix.  Several batches (one per ctx, e.g. one per resident
+ * gauge field) may be driven from different host threads; their work
+ * overlaps on the GPU (each ctx has its own stream).  While a batch is open
+ * its ctx's links, clover and masses must not change (DP_ERR_BAD_STATE). */
+typedef struct {
+  long long tag;   /* the tag given at admission */
+  int slot;        /* the slot that ran it */
+  dp_info info;    /* info.seconds = admission to completion */
+} dp_batch_result;
+
+int dp_batch_open(dp_ctx* ctx, int nslots, int precision, int solver, dp_batch** out);
+void dp_batch_close(dp_batch* b);
+/* Admit ncols right-hand sides (device memory, host layout, one after the
+ * other), all with mass M, the T-entry profile alpha (NULL: the ctx's),
+ * residue r, max_iter, inner reduction delta (0: default), source timeslice
+ * x0_src and a caller tag.  S_dev (nullable, device, host layout, ncols
+ * spinors) receives the restored solutions when they finish.  slots_out
+ * (nullable) receives the ncols slot indices.  DP_ERR_FULL when fewer than
+ * ncols slots are free.  The sources are read before the call returns. */
+int dp_batch_admit(dp_batch* b, int ncols, const void* eta_dev, void* S_dev, double M, const double* alpha, double r,
+                   int max_iter, double delta, int x0_src, long long tag, int* slots_out);
+/* Run k inner iterations for the running slots and the outer steps that
+ * follow; *ndone = results waiting to be harvested. */
+int dp_batch_step(dp_batch* b, int k, int* ndone);
+/* Move up to max finished results (completion order) to out, with their
+ * C_PP (T doubles each, nullable) in cpp; their slots become free. */
+int dp_batch_harvest(dp_batch* b, dp_batch_result* out, double* cpp, int max, int* count);
+int dp_batch_status(const dp_batch* b, int* free_slots, int* running, int* done);
+long long dp_batch_device_bytes(const dp_batch* b);
 
 /* Device bytes a context would hold for the gauge field and clover of a
  * lattice, plus the solver work space for nrhs right-hand sides at the given

@@ -11,7 +11,7 @@ import numpy as np
 from . import _lib as L
 from ._lib import DPError  # noqa: F401
 
-__all__ = ["Lattice", "DPError", "footprint_bytes"]
+__all__ = ["Lattice", "Batch", "DPError", "footprint_bytes"]
 
 
 def _ptr(a):
@@ -163,3 +163,88 @@ class Lattice:
                                   ctypes.c_void_p(stream))
         self._check(rc, allow=(L.DP_ERR_NOT_CONVERGED,) if allow_unconverged else ())
         return cpp, self._infos(info)
+
+
+class Batch:
+    """A set of slots on one Lattice that solve right-hand sides entering and
+    leaving independently (continuous batching).  Sources and solutions are
+    torch CUDA tensors in host layout; results come back with their tag."""
+
+    def __init__(self, lattice, nslots, precision="f32", solver="bicgstab"):
+        self.L = lattice
+        self.nslots = int(nslots)
+        h = ctypes.c_void_p()
+        lattice._check(lattice._L.dp_batch_open(lattice._h, self.nslots, L.DP_PREC[precision],
+                                                L.DP_SOLVER[solver], ctypes.byref(h)))
+        self._h = h
+        self._keep = {}  # tag -> tensors that must stay alive until harvested
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.L._L.dp_batch_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def status(self):
+        f, r, d = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self.L._check(self.L._L.dp_batch_status(self._h, ctypes.byref(f), ctypes.byref(r), ctypes.byref(d)))
+        return dict(free=f.value, running=r.value, done=d.value)
+
+    def device_bytes(self):
+        return int(self.L._L.dp_batch_device_bytes(self._h))
+
+    def admit(self, eta_t, S_t=None, M=0.0, alpha=None, r=1e-10, max_iter=10000, delta=0.0, x0_src=0, tag=0):
+        """Admit the columns of eta_t ([ncols, ...] complex128 CUDA tensor).
+        Returns the slot indices, or None when the batch has too few free slots."""
+        import torch
+        assert eta_t.is_cuda and eta_t.is_contiguous()
+        ncols = eta_t.numel() * eta_t.element_size() // (self.L.V * 12 * 16)
+        a = None if alpha is None else np.ascontiguousarray(alpha, dtype=np.float64)
+        torch.cuda.current_stream(eta_t.device).synchronize()  # the library runs on its own stream
+        slots = (ctypes.c_int * ncols)()
+        rc = self.L._L.dp_batch_admit(self._h, ncols, ctypes.c_void_p(eta_t.data_ptr()),
+                                      ctypes.c_void_p(S_t.data_ptr()) if S_t is not None else None, float(M),
+                                      _ptr(a) if a is not None else None, float(r), int(max_iter), float(delta),
+                                      int(x0_src), int(tag), slots)
+        if rc == L.DP_ERR_FULL:
+            return None
+        self.L._check(rc)
+        if S_t is not None:  # written when the columns finish
+            self._keep.setdefault(int(tag), []).append(S_t)
+        return list(slots)
+
+    def step(self, k=4):
+        n = ctypes.c_int(0)
+        self.L._check(self.L._L.dp_batch_step(self._h, int(k), ctypes.byref(n)))
+        return n.value
+
+    def harvest(self, max_results=None):
+        """Finished right-hand sides: list of dict(tag, slot, info, cpp)."""
+        m = self.nslots if max_results is None else int(max_results)
+        out = (L.dp_batch_result * m)()
+        cpp = np.zeros((m, self.L.T))
+        n = ctypes.c_int(0)
+        self.L._check(self.L._L.dp_batch_harvest(self._h, out, _ptr(cpp), m, ctypes.byref(n)))
+        res = []
+        for k in range(n.value):
+            o = out[k]
+            i = o.info
+            res.append(dict(tag=o.tag, slot=o.slot, cpp=cpp[k].copy(),
+                            info=dict(status=i.status, iters=i.iters, outer=i.outer, hop_calls=i.hop_calls,
+                                      restarts=i.restarts, true_res=i.true_res, seconds=i.seconds)))
+        return res
+
+    def release(self, tag):
+        """Drop the references kept for a finished request."""
+        self._keep.pop(int(tag), None)

@@ -18,6 +18,7 @@ DP_ERR_NOT_CONVERGED = -4
 DP_ERR_BREAKDOWN = -5
 DP_ERR_NONFINITE = -6
 DP_ERR_BAD_STATE = -7
+DP_ERR_FULL = -8
 
 DP_PREC = {"f64": 0, "f32": 1, "f16": 2}
 DP_SOLVER = {"bicgstab": 0, "cgnr": 1}
@@ -29,7 +30,8 @@ DP_APPLY_SCHUR, DP_APPLY_F32, DP_APPLY_F16 = 8, 16, 32
 EXPORTED = [
     "dp_create", "dp_destroy", "dp_last_error", "dp_set_gauge", "dp_set_gauge_dev", "dp_set_clover",
     "dp_set_clover_field", "dp_set_mass", "dp_set_kappa", "dp_set_alpha", "dp_apply", "dp_solve",
-    "dp_solve_dev", "dp_footprint_bytes", "dp_set_timing", "dp_get_timing",
+    "dp_solve_dev", "dp_footprint_bytes", "dp_set_timing", "dp_get_timing", "dp_batch_open", "dp_batch_close",
+    "dp_batch_admit", "dp_batch_step", "dp_batch_harvest", "dp_batch_status", "dp_batch_device_bytes",
 ]
 
 
@@ -48,6 +50,10 @@ class dp_info(ctypes.Structure):
 class dp_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_longlong), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+
+
+class dp_batch_result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_longlong), ("slot", ctypes.c_int), ("info", dp_info)]
 
 
 class DPError(RuntimeError):
@@ -88,5 +94,15 @@ def lib():
     L.dp_footprint_bytes.restype = ctypes.c_longlong
     L.dp_set_timing.argtypes = [vp, ctypes.c_int]
     L.dp_get_timing.argtypes = [vp, ctypes.POINTER(dp_kernel_stat), ctypes.c_int, ip]
+    L.dp_batch_open.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
+    L.dp_batch_close.argtypes = [vp]
+    L.dp_batch_close.restype = None
+    L.dp_batch_admit.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_double, dp, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_double, ctypes.c_int, ctypes.c_longlong, ip]
+    L.dp_batch_step.argtypes = [vp, ctypes.c_int, ip]
+    L.dp_batch_harvest.argtypes = [vp, ctypes.POINTER(dp_batch_result), dp, ctypes.c_int, ip]
+    L.dp_batch_status.argtypes = [vp, ip, ip, ip]
+    L.dp_batch_device_bytes.argtypes = [vp]
+    L.dp_batch_device_bytes.restype = ctypes.c_longlong
     _lib = L
     return L

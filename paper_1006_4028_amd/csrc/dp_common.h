@@ -76,8 +76,11 @@ struct SlotScalars {
   double zz;      // CGNR |z|^2
   double cg_a;    // CGNR step length
   double cg_b;    // CGNR beta
+  double tol2;    // the slot leaves the inner solve once rr <= tol2
+  int iters;      // inner iterations done by the slot (over all its inner solves)
+  int max_iter;   // ... or once iters reaches max_iter
   int breakdown;  // 1: rho collapsed, 2: <rh, v> = 0, 3: omega = 0
-  int pad;
+  int left;       // why it left: 1 converged, 2 breakdown, 3 max_iter, 4 non-finite
 };
 
 // Epilogues of the hop kernel.
@@ -119,6 +122,7 @@ struct ReduceRef {
   double* partials = nullptr;   // [nslots][nblocks][4]
   SlotScalars* sc = nullptr;    // [nslots]
   double* out_sums = nullptr;   // FIN_STORE: [nslots][4]
+  int* inner_mask = nullptr;    // [nslots] cleared when a slot leaves the inner solve
 };
 
 struct HopArgs {

@@ -323,6 +323,21 @@ __device__ __forceinline__ void cdiv(const double* a, const double* b, double* o
   out[1] = im;
 }
 
+// End of an inner iteration: count it and take the slot out of the inner
+// mask when it converged, broke down, ran out of iterations or went non-finite.
+__device__ inline void end_of_iteration(const ReduceRef& red, int slot, SlotScalars& c) {
+  c.iters++;
+  int why = 0;
+  if (!isfinite(c.rr)) why = 4;
+  else if (c.breakdown) why = 2;
+  else if (c.rr <= c.tol2) why = 1;
+  else if (c.iters >= c.max_iter) why = 3;
+  if (why) {
+    c.left = why;
+    if (red.inner_mask) red.inner_mask[slot] = 0;
+  }
+}
+
 // Solver finalisers: turn the folded sums of one slot into its scalars.
 __device__ inline void run_finaliser(const ReduceRef& red, int slot, const double (&s)[4]) {
   if (red.fin == FIN_STORE) {
@@ -335,6 +350,8 @@ __device__ inline void run_finaliser(const ReduceRef& red, int slot, const doubl
       if (s[0] == 0.0 && s[1] == 0.0) {
         c.breakdown = 2;
         c.alpha[0] = c.alpha[1] = 0.0;
+        c.left = 2;
+        if (red.inner_mask) red.inner_mask[slot] = 0;
       } else {
         cdiv(c.rho, s, c.alpha);
       }
@@ -365,6 +382,7 @@ __device__ inline void run_finaliser(const ReduceRef& red, int slot, const doubl
       }
       c.rho[0] = s[0];
       c.rho[1] = s[1];
+      end_of_iteration(red, slot, c);
       break;
     }
     case FIN_BICG_INIT: {
@@ -376,6 +394,7 @@ __device__ inline void run_finaliser(const ReduceRef& red, int slot, const doubl
       c.alpha[1] = c.omega[1] = 0.0;
       c.beta[0] = c.beta[1] = 0.0;
       c.breakdown = 0;
+      c.left = 0;
       break;
     }
     case FIN_CG_ALPHA:
@@ -384,10 +403,12 @@ __device__ inline void run_finaliser(const ReduceRef& red, int slot, const doubl
     case FIN_CG_BETA:
       c.cg_b = c.zz > 0.0 ? s[0] / c.zz : 0.0;
       c.zz = s[0];
+      end_of_iteration(red, slot, c);
       break;
     case FIN_CG_INIT:
       c.zz = s[0];
       c.breakdown = 0;
+      c.left = 0;
       break;
     case FIN_RR:
       c.rr = s[0];

@@ -1,4 +1,5 @@
-// Host runtime of libdp: device buffers, the context, and the batched solver.
+// Host runtime of libdp: device buffers, the context, the batch of slots and
+// the launch helpers shared by the translation units of the runtime.
 #pragma once
 #include <map>
 #include <string>
@@ -72,35 +73,29 @@ struct Field {
   int nslots = 0;
   long slot_stride = 0, scale_stride = 0;
   hipError_t alloc(const Geom& g, int prec_, int nslots_);
-  SpinorRef ref() const {
-    SpinorRef r;
-    r.data = data.p;
-    r.scale = scale.as<float>();
-    r.slot_stride = slot_stride;
-    r.scale_stride = scale_stride;
-    r.prec = prec;
-    return r;
-  }
+  // reference starting at slot s0
+  SpinorRef ref(int s0 = 0) const;
 };
 
 // A per-mass inverse clover A_oo^-1 = (C_oo + 4 + M)^-1 in every precision.
 struct MassEntry {
   double M = 0.0;
   DevBuf a64, a32, a16, s16;
-  bool have32 = false, have16 = false;
 };
 
-// Work space of the batched solver for nslots slots at one inner precision.
+// Device work space of a set of slots at one inner precision.
 struct Workspace {
   int nslots = 0, prec = -1;
-  // FP64
+  // FP64: redefined source (both parities), Schur right-hand side, solution,
+  // FP64 residual, Schur result, odd temporary / odd solution
   Field eta_e, eta_o, b64, x64, r64, t64, to64;
   // inner precision (x in FP32 when the inner precision is FP16)
   Field r, rh, p, v, s, t, x, to;
   // per-slot device tables
-  DevBuf ratio, m4, mask_all, mask_inner, mask_outer, ainv_ptr[3], ainv_scale_ptr, sc, partials, out_sums,
-      slot_scale, x0src, alpha, cpp, sp_aos;
+  DevBuf ratio, m4, mask_inner, mask_outer, ainv_ptr[3], ainv_scale_ptr, sc, partials, out_sums, slot_scale, x0src,
+      alpha, cpp;
   HostBuf h_sc, h_sums, h_mask, h_scale;
+  size_t device_bytes() const;
 };
 
 }  // namespace dp
@@ -121,11 +116,13 @@ struct dp_ctx {
   double csw = 0.0;
   int clover_kind = 0;  // 0: none (c_sw = 0), 1: built from links, 2: caller field
   std::vector<dp::MassEntry*> masses;
+  int open_batches = 0;
 
   double M = 0.0;
   std::vector<double> alpha;
 
-  dp::Workspace ws;
+  dp::Workspace ws_apply;           // one slot, for dp_apply
+  dp_batch* solve_batch = nullptr;  // reused by dp_solve
   dp::DevBuf scratch_aos, bad_flag;
 
   // per-launch HIP-event timing of the library's kernels (dp_set_timing)
@@ -139,10 +136,79 @@ struct dp_ctx {
     hipEvent_t a, b;
   };
   bool timing = false;
+  bool use_graphs = true;
   std::vector<hipEvent_t> ev_free;
   std::vector<Pending> pending;
   std::map<std::string, KStat> kstats;
-  std::map<const void*, int> mask_count;  // active slots of each device mask
+  std::map<const void*, int> mask_count;  // active slots of each device mask (host view)
 
   ~dp_ctx();
 };
+
+struct dp_batch {
+  dp_ctx* c = nullptr;
+  int nslots = 0, prec = 0, solver = 0;
+  dp::Workspace w;
+  enum { FREE = 0, RUNNING = 1, DONE = 2 };
+  struct Slot {
+    int state = FREE;
+    long long tag = 0;
+    void* S_dev = nullptr;
+    dp::MassEntry* me = nullptr;
+    std::vector<double> alpha;
+    double r = 0.0, delta = 0.0;
+    int max_iter = 0, x0 = 0;
+    double eta2 = 0.0, res2 = 0.0, scale = 0.0;
+    int iters = 0, outer = 0, restarts = 0, hops = 0, status = DP_OK;
+    bool in_inner = false, has_inner = false;
+    double t_admit = 0.0, t_done = 0.0;
+    std::vector<double> cpp;
+  };
+  std::vector<Slot> slots;
+  std::vector<int> m_inner, m_outer;  // host copies of the device masks
+  std::vector<int> done_order;        // finished slots in completion order
+  // captured k-iteration graph
+  hipGraphExec_t graph = nullptr;
+  int graph_k = 0;
+  ~dp_batch();
+};
+
+namespace dp {
+namespace rt {
+
+int fail(dp_ctx* c, int code, const char* msg);
+int hip_fail(dp_ctx* c, hipError_t e, const char* expr, int line);
+
+#define DP_HIP(c, expr)                                                      \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess) return dp::rt::hip_fail((c), e_, #expr, __LINE__); \
+  } while (0)
+
+#define DP_TRY(expr)              \
+  do {                            \
+    int rc_ = (expr);             \
+    if (rc_ != DP_OK) return rc_; \
+  } while (0)
+
+double now_s();
+void ratio_tables(int T, int bc_t, const double* alpha, double* out);
+int mass_entry(dp_ctx* c, double M, MassEntry** out);
+int ensure_ws(dp_ctx* c, Workspace& w, int nslots, int prec);
+int h2d(dp_ctx* c, void* dst, const void* src, size_t bytes);
+int upload_mask(dp_ctx* c, Workspace& w, DevBuf& dst, const std::vector<int>& m, int staging);
+int timing_harvest(dp_ctx* c);
+SlotTable slot_table(Workspace& w, int T, int s0, int prec, const int* mask);
+
+// launch helpers over slots [s0, s0 + n) of a workspace
+int hop(dp_ctx* c, Workspace& w, int s0, int n, int prec, int p, int dag, int epi, double sign, const Field& in,
+        const Field& out, const Field* xin, const int* mask, int red = RED_NONE, int fin = FIN_NONE,
+        const Field* wv = nullptr, int* inner_mask = nullptr);
+int blas(dp_ctx* c, Workspace& w, int s0, int n, int op, int prec, const int* mask,
+         std::initializer_list<const Field*> v, int fin = FIN_NONE, int* inner_mask = nullptr);
+// Schur operator Mhat' in -> out (even sites), to = odd temporary
+int schur(dp_ctx* c, Workspace& w, int s0, int n, int prec, int dag, const Field& in, const Field& to,
+          const Field& out, const int* mask, int red, int fin, const Field* wv = nullptr, int* inner_mask = nullptr);
+
+}  // namespace rt
+}  // namespace dp

@@ -1,20 +1,6 @@
-// Host runtime and C ABI of libdp.
-//
-// The solve follows the paper's procedure (field redefinition eq. redeft,
-// preconditioned system eq. linsysprec, restoration) with these building
-// blocks of our own:
-//   * even-odd reduction: the Schur operator Mhat' = A_ee - H_eo A_oo^-1 H_oe
-//     on the even sites (A = 4 + M + C, H the alpha-hop term), so that the
-//     full residual of a solution reconstructed on the odd sites equals the
-//     Schur residual;
-//   * a precision ladder: an FP64 outer loop recomputes r = b - Mhat' x in
-//     FP64 and checks the stopping rule (eq. stopping) on it; an inner Krylov
-//     solve in FP64, FP32 or FP16 storage reduces the normalised residual by
-//     delta; x += |r| e in FP64 (defect correction);
-//   * slots: every right-hand side is a slot with its own scalars, masses and
-//     alpha table on the device.  Slots enter and leave the inner solve
-//     independently; the kernels of one iteration run for all slots in the
-//     inner mask at once (links are shared through the caches).
+// Host runtime of libdp: the context (resident fields, per-mass inverses),
+// the launch helpers, dp_apply and the timing statistics.  The solver over
+// slots lives in batch.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,38 +14,13 @@
 
 using namespace dp;
 
-namespace {
-
-int fail(dp_ctx* c, int code, const char* msg) {
-  if (c) c->err = msg;
-  return code;
-}
-
-#define DP_HIP(c, expr)                                                                       \
-  do {                                                                                        \
-    hipError_t e_ = (expr);                                                                   \
-    if (e_ != hipSuccess) {                                                                   \
-      if (c) {                                                                                \
-        char b_[256];                                                                         \
-        snprintf(b_, sizeof b_, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
-                 __LINE__);                                                                   \
-        (c)->err = b_;                                                                        \
-      }                                                                                       \
-      return e_ == hipErrorOutOfMemory ? DP_ERR_OOM : DP_ERR_DEVICE;                          \
-    }                                                                                         \
-  } while (0)
-
-long storage_units_per_slot(const Geom& g, int prec) {
-  // double2 x12, float4 x6 or uint4 x3 per site
-  return (long)g.Vh * (prec == F64 ? 12 : prec == F32 ? 6 : 3);
-}
-
-}  // namespace
+namespace dp {
 
 hipError_t Field::alloc(const Geom& g, int prec_, int nslots_) {
   prec = prec_;
   nslots = nslots_;
-  slot_stride = storage_units_per_slot(g, prec);
+  // double2 x12, float4 x6 or uint4 x3 per site
+  slot_stride = (long)g.Vh * (prec == F64 ? 12 : prec == F32 ? 6 : 3);
   scale_stride = prec == F16 ? g.Vh : 0;
   hipError_t e = data.reserve((size_t)nslots * g.Vh * spinor_site_bytes(prec));
   if (e != hipSuccess) return e;
@@ -67,19 +28,43 @@ hipError_t Field::alloc(const Geom& g, int prec_, int nslots_) {
   return e;
 }
 
-dp_ctx::~dp_ctx() {
-  for (auto& q : pending) {
-    (void)hipEventDestroy(q.a);
-    (void)hipEventDestroy(q.b);
-  }
-  for (auto e : ev_free) (void)hipEventDestroy(e);
-  for (auto* m : masses) delete m;
-  if (stream) (void)hipStreamDestroy(stream);
+SpinorRef Field::ref(int s0) const {
+  SpinorRef r;
+  const size_t unit = prec == F64 ? sizeof(double2) : prec == F32 ? sizeof(float4) : sizeof(uint4);
+  r.data = data.p ? static_cast<char*>(data.p) + (size_t)s0 * slot_stride * unit : nullptr;
+  r.scale = scale.p ? scale.as<float>() + (size_t)s0 * scale_stride : nullptr;
+  r.slot_stride = slot_stride;
+  r.scale_stride = scale_stride;
+  r.prec = prec;
+  return r;
 }
 
-namespace {
+size_t Workspace::device_bytes() const {
+  const Field* f[] = {&eta_e, &eta_o, &b64, &x64, &r64, &t64, &to64, &r, &rh, &p, &v, &s, &t, &x, &to};
+  size_t b = 0;
+  for (const Field* q : f) b += q->data.bytes + q->scale.bytes;
+  return b;
+}
 
-// ------------------------------------------------------------- helpers
+namespace rt {
+
+int fail(dp_ctx* c, int code, const char* msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(dp_ctx* c, hipError_t e, const char* expr, int line) {
+  if (c) {
+    char b[320];
+    snprintf(b, sizeof b, "%s failed: %s (line %d)", expr, hipGetErrorString(e), line);
+    c->err = b;
+  }
+  return e == hipErrorOutOfMemory ? DP_ERR_OOM : DP_ERR_DEVICE;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 // ratio tables of the modified time hops for one alpha table:
 //   fwd[x0] = s_f alpha(x0)/alpha(x0+1), bwd[x0] = s_b alpha(x0)/alpha(x0-1),
@@ -97,11 +82,6 @@ void ratio_tables(int T, int bc_t, const double* alpha, double* out) {
   }
 }
 
-int check_state(dp_ctx* c) {
-  if (!c->have_U[F64]) return fail(c, DP_ERR_BAD_STATE, "gauge field not set");
-  return DP_OK;
-}
-
 // Per-mass A_oo^-1 in every precision (cached per (field, clover, M)).
 int mass_entry(dp_ctx* c, double M, MassEntry** out) {
   for (auto* m : c->masses)
@@ -113,8 +93,7 @@ int mass_entry(dp_ctx* c, double M, MassEntry** out) {
   auto* m = new (std::nothrow) MassEntry;
   if (!m) return fail(c, DP_ERR_OOM, "host allocation failed");
   m->M = M;
-  const size_t n64 = (size_t)g.Vh * clover_site_bytes(F64);
-  hipError_t e = m->a64.reserve(n64);
+  hipError_t e = m->a64.reserve((size_t)g.Vh * clover_site_bytes(F64));
   if (e == hipSuccess) e = m->a32.reserve((size_t)g.Vh * clover_site_bytes(F32));
   if (e == hipSuccess) e = m->a16.reserve((size_t)g.Vh * clover_site_bytes(F16));
   if (e == hipSuccess) e = m->s16.reserve((size_t)g.Vh * sizeof(float));
@@ -140,9 +119,273 @@ int mass_entry(dp_ctx* c, double M, MassEntry** out) {
   return DP_OK;
 }
 
-void drop_masses(dp_ctx* c) {
+int ensure_ws(dp_ctx* c, Workspace& w, int nslots, int prec) {
+  const Geom& g = c->g;
+  if (w.nslots >= nslots && w.prec == prec) return DP_OK;
+  const int n = std::max(nslots, w.nslots);
+  const int px = prec == F16 ? F32 : prec;
+  Field* f64s[] = {&w.eta_e, &w.eta_o, &w.b64, &w.x64, &w.r64, &w.t64, &w.to64};
+  for (Field* f : f64s) DP_HIP(c, f->alloc(g, F64, n));
+  Field* fin[] = {&w.r, &w.rh, &w.p, &w.v, &w.s, &w.t, &w.to};
+  for (Field* f : fin) DP_HIP(c, f->alloc(g, prec, n));
+  DP_HIP(c, w.x.alloc(g, px, n));
+  const int nb = std::max(reduction_blocks(g), hop_blocks(g));
+  DP_HIP(c, w.ratio.reserve(sizeof(double) * 4 * g.T * n));
+  DP_HIP(c, w.m4.reserve(sizeof(double) * n));
+  DP_HIP(c, w.mask_inner.reserve(sizeof(int) * n));
+  DP_HIP(c, w.mask_outer.reserve(sizeof(int) * n));
+  for (int k = 0; k < 3; ++k) DP_HIP(c, w.ainv_ptr[k].reserve(sizeof(void*) * n));
+  DP_HIP(c, w.ainv_scale_ptr.reserve(sizeof(float*) * n));
+  DP_HIP(c, w.sc.reserve(sizeof(SlotScalars) * n));
+  DP_HIP(c, w.partials.reserve(sizeof(double) * 4 * nb * n));
+  DP_HIP(c, w.out_sums.reserve(sizeof(double) * 4 * n));
+  DP_HIP(c, w.slot_scale.reserve(sizeof(double) * n));
+  DP_HIP(c, w.x0src.reserve(sizeof(int) * n));
+  DP_HIP(c, w.alpha.reserve(sizeof(double) * g.T * n));
+  DP_HIP(c, w.cpp.reserve(sizeof(double) * g.T * n));
+  DP_HIP(c, w.h_sc.reserve(sizeof(SlotScalars) * n));
+  DP_HIP(c, w.h_sums.reserve(sizeof(double) * 4 * n));
+  DP_HIP(c, w.h_mask.reserve(sizeof(int) * 4 * n));
+  DP_HIP(c, w.h_scale.reserve(sizeof(double) * (4 * g.T + 8) * n));
+  DP_HIP(c, hipMemsetAsync(w.mask_inner.p, 0, sizeof(int) * n, c->stream));
+  DP_HIP(c, hipMemsetAsync(w.mask_outer.p, 0, sizeof(int) * n, c->stream));
+  DP_HIP(c, hipMemsetAsync(w.sc.p, 0, sizeof(SlotScalars) * n, c->stream));
+  DP_HIP(c, hipStreamSynchronize(c->stream));
+  w.nslots = n;
+  w.prec = prec;
+  return DP_OK;
+}
+
+// host -> device copy on the ctx stream, complete on return
+int h2d(dp_ctx* c, void* dst, const void* src, size_t bytes) {
+  DP_HIP(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+  DP_HIP(c, hipStreamSynchronize(c->stream));
+  return DP_OK;
+}
+
+// Upload a host mask through its own pinned staging row; each row is only
+// rewritten after a later stream synchronisation.
+int upload_mask(dp_ctx* c, Workspace& w, DevBuf& dst, const std::vector<int>& m, int staging) {
+  int cnt = 0;
+  for (int v : m) cnt += v != 0;
+  c->mask_count[dst.p] = cnt;
+  int* h = w.h_mask.as<int>() + (size_t)staging * w.nslots;
+  std::memcpy(h, m.data(), sizeof(int) * m.size());
+  DP_HIP(c, hipMemcpyAsync(dst.p, h, sizeof(int) * m.size(), hipMemcpyHostToDevice, c->stream));
+  return DP_OK;
+}
+
+// ----------------------------------------------------------- launch timing
+
+namespace {
+
+const char* prec_name(int p) { return p == F64 ? "f64" : p == F32 ? "f32" : "f16"; }
+
+int active_slots(dp_ctx* c, const int* mask, int n) {
+  if (!mask) return n;
+  auto it = c->mask_count.find(mask);
+  return it == c->mask_count.end() ? n : std::min(n, it->second);
+}
+
+int timing_begin(dp_ctx* c, hipEvent_t* a) {
+  if (!c->timing) return DP_OK;
+  if (c->ev_free.size() < 2) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      DP_HIP(c, hipEventCreate(&e));
+      c->ev_free.push_back(e);
+    }
+  }
+  *a = c->ev_free.back();
+  c->ev_free.pop_back();
+  DP_HIP(c, hipEventRecord(*a, c->stream));
+  return DP_OK;
+}
+
+int timing_end(dp_ctx* c, hipEvent_t a, const std::string& name, double bytes, double flops) {
+  if (!c->timing) return DP_OK;
+  hipEvent_t b = c->ev_free.back();
+  c->ev_free.pop_back();
+  DP_HIP(c, hipEventRecord(b, c->stream));
+  c->pending.push_back({name, bytes, flops, a, b});
+  return DP_OK;
+}
+
+// Algorithmic HBM bytes of one hop launch: each link, clover block and input
+// spinor once, each output once.  Per output site: 8 links (144 reals, shared by
+// the slots), per active slot the input (24) and output (24) spinors, the
+// clover block pair (72 reals) for the epilogues that use it, the epilogue
+// input (24 per slot) and the dot partner (24 per slot); FP16 adds the 4-byte
+// per-site scales.  Flops: 1320 per site and slot for the hop, 552 for a
+// clover block pair, 48 for the epilogue axpy and 96 for a fused dot.
+void hop_cost(dp_ctx* c, int prec, int epi, int red, int nact, double* bytes, double* flops) {
+  const double b = prec == F64 ? 8.0 : prec == F32 ? 4.0 : 2.0;
+  const double sc = prec == F16 ? 4.0 : 0.0;
+  const double Vh = c->g.Vh;
+  double site = 144 * b;
+  double slot = 2 * (24 * b + sc);
+  double fl = 1320;
+  if (epi == EPI_INV || epi == EPI_INV_SUB || epi == EPI_DIAG) {
+    site += 72 * b + sc;
+    fl += 552;
+  }
+  if (epi == EPI_DIAG || epi == EPI_SUB || epi == EPI_INV_SUB) {
+    slot += 24 * b + sc;
+    fl += 48;
+  }
+  if (red == RED_DOT_EXT) {
+    slot += 24 * b + sc;
+    fl += 96;
+  } else if (red != RED_NONE) {
+    fl += 96;
+  }
+  *bytes = Vh * (site + nact * slot);
+  *flops = Vh * nact * fl;
+}
+
+// reductions of the slots [s0, ...) of a workspace
+ReduceRef reduce_ref(Workspace& w, int s0, int red, int fin, int* inner_mask) {
+  ReduceRef r;
+  r.red = red;
+  r.fin = fin;
+  r.partials = w.partials.as<double>();  // indexed by the slot within the launch
+  r.sc = w.sc.as<SlotScalars>() + s0;
+  r.out_sums = w.out_sums.as<double>() + (size_t)4 * s0;
+  r.inner_mask = inner_mask ? inner_mask + s0 : nullptr;
+  return r;
+}
+
+}  // namespace
+
+// per-slot tables of the slots [s0, ...) of a workspace
+SlotTable slot_table(Workspace& w, int T, int s0, int prec, const int* mask) {
+  SlotTable t;
+  t.ratio = w.ratio.as<double>() + (size_t)s0 * 4 * T;
+  t.m4 = w.m4.as<double>() + s0;
+  t.mask = mask ? mask + s0 : nullptr;
+  t.ainv = static_cast<const void* const*>(w.ainv_ptr[prec].p) + s0;
+  t.ainv_scale = prec == F16 ? static_cast<const float* const*>(w.ainv_scale_ptr.p) + s0 : nullptr;
+  return t;
+}
+
+int timing_harvest(dp_ctx* c) {
+  for (auto& q : c->pending) {
+    float ms = 0.f;
+    DP_HIP(c, hipEventSynchronize(q.b));
+    DP_HIP(c, hipEventElapsedTime(&ms, q.a, q.b));
+    auto& k = c->kstats[q.name];
+    k.launches++;
+    k.ms += ms;
+    k.bytes += q.bytes;
+    k.flops += q.flops;
+    c->ev_free.push_back(q.a);
+    c->ev_free.push_back(q.b);
+  }
+  c->pending.clear();
+  return DP_OK;
+}
+
+int hop(dp_ctx* c, Workspace& w, int s0, int n, int prec, int p, int dag, int epi, double sign, const Field& in,
+        const Field& out, const Field* xin, const int* mask, int red, int fin, const Field* wv, int* inner_mask) {
+  HopArgs a;
+  a.g = c->g;
+  a.p = p;
+  a.dag = dag;
+  a.epi = epi;
+  a.sign = sign;
+  a.U_out = c->U[prec][p].p;
+  a.U_in = c->U[prec][1 - p].p;
+  a.link_prec = prec;
+  a.in = in.ref(s0);
+  a.out = out.ref(s0);
+  if (xin) a.xin = xin->ref(s0);
+  a.clov.prec = prec;
+  a.clov.data = prec == F64 ? c->C64[p].p : prec == F32 ? c->C32[p].p : c->C16[p].p;
+  a.clov.scale = prec == F16 ? c->C16s[p].as<float>() : nullptr;
+  a.slots = slot_table(w, c->g.T, s0, prec, mask);
+  a.red = reduce_ref(w, s0, red, fin, inner_mask);
+  if (wv) a.red.w = wv->ref(s0);
+  a.nslots = n;
+  hipEvent_t ev = nullptr;
+  DP_TRY(timing_begin(c, &ev));
+  DP_HIP(c, launch_hop(a, c->stream));
+  if (c->timing) {
+    static const char* epi_names[] = {"hop", "inv", "diag", "sub", "invsub"};
+    double bytes, flops;
+    hop_cost(c, prec, epi, red, active_slots(c, mask, n), &bytes, &flops);
+    std::string name = std::string("hop_") + prec_name(prec) + "_" + epi_names[epi] + (dag ? "_dag" : "");
+    DP_TRY(timing_end(c, ev, name, bytes, flops));
+  }
+  return DP_OK;
+}
+
+int blas(dp_ctx* c, Workspace& w, int s0, int n, int op, int prec, const int* mask,
+         std::initializer_list<const Field*> v, int fin, int* inner_mask) {
+  BlasArgs a;
+  a.g = c->g;
+  a.nslots = n;
+  a.prec = prec;
+  a.mask = mask ? mask + s0 : nullptr;
+  a.sc = w.sc.as<SlotScalars>() + s0;
+  a.slot_scale = w.slot_scale.as<double>() + s0;
+  int k = 0;
+  for (const Field* f : v) {
+    if (f) a.v[k] = f->ref(s0);
+    ++k;
+  }
+  a.red = reduce_ref(w, s0, RED_NONE, fin, inner_mask);
+  hipEvent_t ev = nullptr;
+  DP_TRY(timing_begin(c, &ev));
+  DP_HIP(c, launch_blas(op, a, c->stream));
+  if (c->timing) {
+    // vectors read + written per site and slot
+    static const int nvec[] = {1, 2, 5, 4, 3, 7, 6, 3, 2, 3, 3, 1, 2};
+    const double b = prec == F64 ? 8.0 : prec == F32 ? 4.0 : 2.0;
+    const double bytes = (double)c->g.Vh * active_slots(c, mask, n) * nvec[op] * 24 * b;
+    DP_TRY(timing_end(c, ev, std::string("blas_") + prec_name(prec) + "_" + std::to_string(op), bytes, 0.0));
+  }
+  return DP_OK;
+}
+
+int schur(dp_ctx* c, Workspace& w, int s0, int n, int prec, int dag, const Field& in, const Field& to, const Field& out,
+          const int* mask, int red, int fin, const Field* wv, int* inner_mask) {
+  DP_TRY(hop(c, w, s0, n, prec, 1, dag, EPI_INV, 0.0, in, to, nullptr, mask));
+  DP_TRY(hop(c, w, s0, n, prec, 0, dag, EPI_DIAG, -1.0, to, out, &in, mask, red, fin, wv, inner_mask));
+  return DP_OK;
+}
+
+}  // namespace rt
+}  // namespace dp
+
+using namespace dp::rt;
+
+dp_ctx::~dp_ctx() {
+  for (auto& q : pending) {
+    (void)hipEventDestroy(q.a);
+    (void)hipEventDestroy(q.b);
+  }
+  for (auto e : ev_free) (void)hipEventDestroy(e);
+  for (auto* m : masses) delete m;
+  if (stream) (void)hipStreamDestroy(stream);
+}
+
+namespace {
+
+int check_state(dp_ctx* c) {
+  if (!c->have_U[F64]) return fail(c, DP_ERR_BAD_STATE, "gauge field not set");
+  return DP_OK;
+}
+
+// the cached inverses depend on links and clover; a batch holds pointers to them
+int drop_masses(dp_ctx* c) {
+  if (c->solve_batch) {  // the batch dp_solve keeps between calls
+    dp_batch_close(c->solve_batch);
+    c->solve_batch = nullptr;
+  }
+  if (c->open_batches > 0) return fail(c, DP_ERR_BAD_STATE, "a batch is open on this context");
   for (auto* m : c->masses) delete m;
   c->masses.clear();
+  return DP_OK;
 }
 
 // zero clover (c_sw = 0) in every precision
@@ -170,509 +413,9 @@ int clover_convert_all(dp_ctx* c) {
   return DP_OK;
 }
 
-CloverRef clover_ref(dp_ctx* c, int p, int prec) {
-  CloverRef r;
-  r.prec = prec;
-  if (prec == F64) r.data = c->C64[p].p;
-  if (prec == F32) r.data = c->C32[p].p;
-  if (prec == F16) {
-    r.data = c->C16[p].p;
-    r.scale = c->C16s[p].as<float>();
-  }
-  return r;
-}
-
-// ------------------------------------------------------------- workspace
-
-int ensure_ws(dp_ctx* c, int nslots, int prec) {
-  Workspace& w = c->ws;
-  const Geom& g = c->g;
-  if (w.nslots < nslots || w.prec != prec) {
-    const int n = nslots > w.nslots ? nslots : w.nslots;
-    const int px = prec == F16 ? F32 : prec;
-    Field* f64s[] = {&w.eta_e, &w.eta_o, &w.b64, &w.x64, &w.r64, &w.t64, &w.to64};
-    for (Field* f : f64s) DP_HIP(c, f->alloc(g, F64, n));
-    Field* fin[] = {&w.r, &w.rh, &w.p, &w.v, &w.s, &w.t, &w.to};
-    for (Field* f : fin) DP_HIP(c, f->alloc(g, prec, n));
-    DP_HIP(c, w.x.alloc(g, px, n));
-    const int nb = std::max(reduction_blocks(g), hop_blocks(g));
-    DP_HIP(c, w.ratio.reserve(sizeof(double) * 4 * g.T * n));
-    DP_HIP(c, w.m4.reserve(sizeof(double) * n));
-    DP_HIP(c, w.mask_all.reserve(sizeof(int) * n));
-    DP_HIP(c, w.mask_inner.reserve(sizeof(int) * n));
-    DP_HIP(c, w.mask_outer.reserve(sizeof(int) * n));
-    for (int k = 0; k < 3; ++k) DP_HIP(c, w.ainv_ptr[k].reserve(sizeof(void*) * n));
-    DP_HIP(c, w.ainv_scale_ptr.reserve(sizeof(float*) * n));
-    DP_HIP(c, w.sc.reserve(sizeof(SlotScalars) * n));
-    DP_HIP(c, w.partials.reserve(sizeof(double) * 4 * nb * n));
-    DP_HIP(c, w.out_sums.reserve(sizeof(double) * 4 * n));
-    DP_HIP(c, w.slot_scale.reserve(sizeof(double) * n));
-    DP_HIP(c, w.x0src.reserve(sizeof(int) * n));
-    DP_HIP(c, w.alpha.reserve(sizeof(double) * g.T * n));
-    DP_HIP(c, w.cpp.reserve(sizeof(double) * g.T * n));
-    DP_HIP(c, w.h_sc.reserve(sizeof(SlotScalars) * n));
-    DP_HIP(c, w.h_sums.reserve(sizeof(double) * 4 * n));
-    DP_HIP(c, w.h_mask.reserve(sizeof(int) * 3 * n));
-    DP_HIP(c, w.h_scale.reserve(sizeof(double) * (4 * g.T + 4) * n));
-    w.nslots = n;
-    w.prec = prec;
-  }
-  return DP_OK;
-}
-
-#define DP_TRY(expr)              \
-  do {                            \
-    int rc_ = (expr);             \
-    if (rc_ != DP_OK) return rc_; \
-  } while (0)
-
-// host -> device copy on the ctx stream, complete on return
-int h2d(dp_ctx* c, void* dst, const void* src, size_t bytes) {
-  DP_HIP(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
-  DP_HIP(c, hipStreamSynchronize(c->stream));
-  return DP_OK;
-}
-
-// Upload per-slot tables: alpha (one table for all), m4, A^-1 pointers, x0src.
-int upload_slot_tables(dp_ctx* c, int nslots, const double* alpha, MassEntry* me, int x0src) {
-  Workspace& w = c->ws;
-  const int T = c->g.T;
-  double* h = w.h_scale.as<double>();  // staging: [nslots][4T] ratios, then [nslots][T] alpha
-  std::vector<double> rt(4 * T);
-  ratio_tables(T, c->bc_t, alpha, rt.data());
-  for (int s = 0; s < nslots; ++s) std::memcpy(h + (size_t)s * 4 * T, rt.data(), sizeof(double) * 4 * T);
-  DP_HIP(c, hipMemcpyAsync(w.ratio.p, h, sizeof(double) * 4 * T * nslots, hipMemcpyHostToDevice, c->stream));
-  DP_HIP(c, hipStreamSynchronize(c->stream));
-  for (int s = 0; s < nslots; ++s) std::memcpy(h + (size_t)s * T, alpha, sizeof(double) * T);
-  DP_HIP(c, hipMemcpyAsync(w.alpha.p, h, sizeof(double) * T * nslots, hipMemcpyHostToDevice, c->stream));
-  DP_HIP(c, hipStreamSynchronize(c->stream));
-  std::vector<double> m4(nslots, 4.0 + me->M);
-  std::vector<const void*> p64(nslots, me->a64.p), p32(nslots, me->a32.p), p16(nslots, me->a16.p);
-  std::vector<const float*> s16(nslots, me->s16.as<float>());
-  std::vector<int> x0(nslots, x0src);
-  DP_TRY(h2d(c, w.m4.p, m4.data(), sizeof(double) * nslots));
-  DP_TRY(h2d(c, w.ainv_ptr[F64].p, p64.data(), sizeof(void*) * nslots));
-  DP_TRY(h2d(c, w.ainv_ptr[F32].p, p32.data(), sizeof(void*) * nslots));
-  DP_TRY(h2d(c, w.ainv_ptr[F16].p, p16.data(), sizeof(void*) * nslots));
-  DP_TRY(h2d(c, w.ainv_scale_ptr.p, s16.data(), sizeof(float*) * nslots));
-  DP_TRY(h2d(c, w.x0src.p, x0.data(), sizeof(int) * nslots));
-  return DP_OK;
-}
-
-int upload_mask(dp_ctx* c, DevBuf& dst, const std::vector<int>& m, int slot_in_staging) {
-  int cnt = 0;
-  for (int v : m) cnt += v != 0;
-  c->mask_count[dst.p] = cnt;
-  int* h = c->ws.h_mask.as<int>() + (size_t)slot_in_staging * c->ws.nslots;
-  std::memcpy(h, m.data(), sizeof(int) * m.size());
-  DP_HIP(c, hipMemcpyAsync(dst.p, h, sizeof(int) * m.size(), hipMemcpyHostToDevice, c->stream));
-  return DP_OK;
-}
-
-SlotTable slot_table(dp_ctx* c, int prec, const int* mask) {
-  Workspace& w = c->ws;
-  SlotTable t;
-  t.ratio = w.ratio.as<double>();
-  t.m4 = w.m4.as<double>();
-  t.mask = mask;
-  t.ainv = static_cast<const void* const*>(w.ainv_ptr[prec].p);
-  t.ainv_scale = prec == F16 ? static_cast<const float* const*>(w.ainv_scale_ptr.p) : nullptr;
-  return t;
-}
-
-ReduceRef reduce_ref(dp_ctx* c, int red, int fin) {
-  Workspace& w = c->ws;
-  ReduceRef r;
-  r.red = red;
-  r.fin = fin;
-  r.partials = w.partials.as<double>();
-  r.sc = w.sc.as<SlotScalars>();
-  r.out_sums = w.out_sums.as<double>();
-  return r;
-}
-
-// ----------------------------------------------------------- launch timing
-
-const char* prec_name(int p) { return p == F64 ? "f64" : p == F32 ? "f32" : "f16"; }
-
-int active_slots(dp_ctx* c, const int* mask, int nslots) {
-  auto it = c->mask_count.find(mask);
-  return it == c->mask_count.end() ? nslots : it->second;
-}
-
-int timing_begin(dp_ctx* c, hipEvent_t* a) {
-  if (!c->timing) return DP_OK;
-  if (c->ev_free.size() < 2) {
-    for (int k = 0; k < 64; ++k) {
-      hipEvent_t e;
-      DP_HIP(c, hipEventCreate(&e));
-      c->ev_free.push_back(e);
-    }
-  }
-  *a = c->ev_free.back();
-  c->ev_free.pop_back();
-  DP_HIP(c, hipEventRecord(*a, c->stream));
-  return DP_OK;
-}
-
-int timing_end(dp_ctx* c, hipEvent_t a, const std::string& name, double bytes, double flops) {
-  if (!c->timing) return DP_OK;
-  hipEvent_t b = c->ev_free.back();
-  c->ev_free.pop_back();
-  DP_HIP(c, hipEventRecord(b, c->stream));
-  c->pending.push_back({name, bytes, flops, a, b});
-  return DP_OK;
-}
-
-// fold finished launches into the per-kernel statistics (after a stream sync)
-int timing_harvest(dp_ctx* c) {
-  for (auto& q : c->pending) {
-    float ms = 0.f;
-    DP_HIP(c, hipEventSynchronize(q.b));
-    DP_HIP(c, hipEventElapsedTime(&ms, q.a, q.b));
-    auto& k = c->kstats[q.name];
-    k.launches++;
-    k.ms += ms;
-    k.bytes += q.bytes;
-    k.flops += q.flops;
-    c->ev_free.push_back(q.a);
-    c->ev_free.push_back(q.b);
-  }
-  c->pending.clear();
-  return DP_OK;
-}
-
-// Algorithmic HBM bytes of one hop launch: each link, clover block and input
-// spinor once, each output once.  Per output site: 8 links (144 reals, shared by
-// the slots), per active slot the input (24) and output (24) spinors, the
-// clover block pair (72 reals) for the epilogues that use it, the epilogue
-// input (24 per slot) and the dot partner (24 per slot); FP16 adds the 4-byte
-// per-site scales.  Flops: 1320 per site and slot for the hop, 552 for a
-// clover block pair, 48 for the epilogue axpy and 8-16 for a fused dot.
-void hop_cost(dp_ctx* c, int prec, int epi, int red, int nact, double* bytes, double* flops) {
-  const double b = prec == F64 ? 8.0 : prec == F32 ? 4.0 : 2.0;
-  const double sc = prec == F16 ? 4.0 : 0.0;
-  const double Vh = c->g.Vh;
-  double site = 144 * b;
-  double slot = 2 * (24 * b + sc);
-  double fl = 1320;
-  if (epi == EPI_INV || epi == EPI_INV_SUB || epi == EPI_DIAG) {
-    site += 72 * b + sc;
-    fl += 552;
-  }
-  if (epi == EPI_DIAG || epi == EPI_SUB || epi == EPI_INV_SUB) {
-    slot += 24 * b + sc;
-    fl += 48;
-  }
-  if (red == RED_DOT_EXT) {
-    slot += 24 * b + sc;
-    fl += 96;
-  } else if (red != RED_NONE) {
-    fl += 96;
-  }
-  *bytes = Vh * (site + nact * slot);
-  *flops = Vh * nact * fl;
-}
-
-// one hop launch; p = output parity
-int hop(dp_ctx* c, int nslots, int prec, int p, int dag, int epi, double sign, const Field& in, const Field& out,
-        const Field* xin, const int* mask, int red = RED_NONE, int fin = FIN_NONE, const Field* w = nullptr) {
-  HopArgs a;
-  a.g = c->g;
-  a.p = p;
-  a.dag = dag;
-  a.epi = epi;
-  a.sign = sign;
-  a.U_out = c->U[prec][p].p;
-  a.U_in = c->U[prec][1 - p].p;
-  a.link_prec = prec;
-  a.in = in.ref();
-  a.out = out.ref();
-  if (xin) a.xin = xin->ref();
-  a.clov = clover_ref(c, p, prec);
-  a.slots = slot_table(c, prec, mask);
-  a.red = reduce_ref(c, red, fin);
-  if (w) a.red.w = w->ref();
-  a.nslots = nslots;
-  hipEvent_t ev = nullptr;
-  DP_TRY(timing_begin(c, &ev));
-  DP_HIP(c, launch_hop(a, c->stream));
-  if (c->timing) {
-    static const char* epi_names[] = {"hop", "inv", "diag", "sub", "invsub"};
-    double bytes, flops;
-    hop_cost(c, prec, epi, red, active_slots(c, mask, nslots), &bytes, &flops);
-    std::string name = std::string("hop_") + prec_name(prec) + "_" + epi_names[epi] + (dag ? "_dag" : "");
-    DP_TRY(timing_end(c, ev, name, bytes, flops));
-  }
-  return DP_OK;
-}
-
-int blas(dp_ctx* c, int op, int nslots, int prec, const int* mask, std::initializer_list<const Field*> v,
-         int fin = FIN_NONE) {
-  BlasArgs a;
-  a.g = c->g;
-  a.nslots = nslots;
-  a.prec = prec;
-  a.mask = mask;
-  a.sc = c->ws.sc.as<SlotScalars>();
-  a.slot_scale = c->ws.slot_scale.as<double>();
-  int k = 0;
-  for (const Field* f : v) {
-    if (f) a.v[k] = f->ref();
-    ++k;
-  }
-  a.red = reduce_ref(c, RED_NONE, fin);
-  hipEvent_t ev = nullptr;
-  DP_TRY(timing_begin(c, &ev));
-  DP_HIP(c, launch_blas(op, a, c->stream));
-  if (c->timing) {
-    // vectors read + written per site and slot (FP64 ones counted at 8 bytes)
-    static const int nvec[] = {1, 2, 5, 4, 3, 7, 6, 3, 2, 3, 3, 1, 2};
-    const double b = prec == F64 ? 8.0 : prec == F32 ? 4.0 : 2.0;
-    const double bytes = (double)c->g.Vh * active_slots(c, mask, nslots) * nvec[op] * 24 * b;
-    DP_TRY(timing_end(c, ev, std::string("blas_") + prec_name(prec) + "_" + std::to_string(op), bytes, 0.0));
-  }
-  return DP_OK;
-}
-
-// Mhat' in -> out (Schur operator on even sites), in prec; to = odd temporary
-int schur(dp_ctx* c, int n, int prec, int dag, const Field& in, const Field& to, const Field& out, const int* mask,
-          int red, int fin, const Field* w = nullptr) {
-  DP_TRY(hop(c, n, prec, 1, dag, EPI_INV, 0.0, in, to, nullptr, mask));
-  DP_TRY(hop(c, n, prec, 0, dag, EPI_DIAG, -1.0, to, out, &in, mask, red, fin, w));
-  return DP_OK;
-}
-
-struct SlotHost {
-  int done = 0, in_inner = 0, has_inner = 0;
-  int iters = 0, outer = 0, restarts = 0, hops = 0;
-  int status = DP_OK;
-  double eta2 = 0.0, res2 = 0.0, scale = 0.0, tol2 = 0.0;
-};
-
-// ------------------------------------------------------------- the solve
-
-int run_solve(dp_ctx* c, const double2* eta_dev, int n, const dp_params& P, double2* S_dev, double* cpp_out,
-              dp_info* info) {
-  const auto t_start = std::chrono::steady_clock::now();
-  const int prec = P.precision;
-  const int px = prec == F16 ? F32 : prec;
-  (void)px;
-  DP_TRY(ensure_ws(c, n, prec));
-  MassEntry* me = nullptr;
-  DP_TRY(mass_entry(c, c->M, &me));
-  DP_TRY(upload_slot_tables(c, n, c->alpha.data(), me, P.x0_src));
-  Workspace& w = c->ws;
-  const Geom& g = c->g;
-  const int* m_all = w.mask_all.as<int>();
-  const int* m_in = w.mask_inner.as<int>();
-  const int* m_out = w.mask_outer.as<int>();
-  std::vector<int> all(n, 1), inner(n, 0), outer(n, 0);
-  DP_TRY(upload_mask(c, w.mask_all, all, 0));
-
-  // eta' = alpha eta on both parities, |eta'|^2 per slot
-  DP_HIP(c, launch_spinor_import(g, eta_dev, n, 2L * g.Vh * 12, 0, w.eta_e.ref(), w.alpha.as<double>(), c->stream));
-  DP_HIP(c, launch_spinor_import(g, eta_dev, n, 2L * g.Vh * 12, 1, w.eta_o.ref(), w.alpha.as<double>(), c->stream));
-  std::vector<SlotHost> hs(n);
-  double* sums = w.h_sums.as<double>();
-  for (int par = 0; par < 2; ++par) {
-    DP_TRY(blas(c, OP_NORM, n, F64, m_all, {nullptr, par ? &w.eta_o : &w.eta_e}, FIN_STORE));
-    DP_HIP(c, hipMemcpyAsync(sums, w.out_sums.p, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, c->stream));
-    DP_HIP(c, hipStreamSynchronize(c->stream));
-    for (int s = 0; s < n; ++s) hs[s].eta2 += sums[4 * s];
-  }
-  for (int s = 0; s < n; ++s)
-    if (!std::isfinite(hs[s].eta2)) return fail(c, DP_ERR_NONFINITE, "source contains NaN or Inf");
-
-  // Schur right-hand side b = eta'_e - H_eo A_oo^-1 eta'_o, x = 0
-  {
-    SlotTable st = slot_table(c, F64, m_all);
-    DP_HIP(c, launch_clover_apply(g, st, w.eta_o.ref(), w.to64.ref(), n, c->stream));
-  }
-  DP_TRY(hop(c, n, F64, 0, 0, EPI_SUB, 0.0, w.to64, w.b64, &w.eta_e, m_all));
-  DP_TRY(blas(c, OP_ZERO, n, F64, m_all, {&w.x64}));
-  for (int s = 0; s < n; ++s) hs[s].hops = 2;  // source preparation and odd reconstruction
-
-  const double r2 = P.r * P.r;
-  const double delta = P.delta > 0 ? P.delta : (prec == F16 ? 5e-3 : 1e-5);
-  const int cgnr = P.solver == DP_SOLVER_CGNR;
-  SlotScalars* hsc = w.h_sc.as<SlotScalars>();
-  double* hscale = w.h_scale.as<double>();
-
-  // outer step for the slots in `pend`: x += |r| e (when an inner result exists),
-  // r = b - Mhat' x in FP64, the stopping test, and the start of the next inner solve
-  auto outer_step = [&](const std::vector<int>& pend) -> int {
-    for (int s = 0; s < n; ++s) outer[s] = pend[s];
-    DP_TRY(upload_mask(c, w.mask_outer, outer, 1));
-    bool any_prev = false;
-    for (int s = 0; s < n; ++s) {
-      hscale[s] = pend[s] && hs[s].has_inner ? hs[s].scale : 0.0;
-      any_prev |= pend[s] && hs[s].has_inner;
-    }
-    if (any_prev) {
-      DP_HIP(c, hipMemcpyAsync(w.slot_scale.p, hscale, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
-      // slots without an inner result get a zero scale; their x buffer is still finite
-      // because every inner start zeroes it, and the first outer step skips this
-      DP_TRY(blas(c, OP_AXPY_SCALED, n, prec, m_out, {&w.x64, &w.x}));
-    }
-    DP_TRY(schur(c, n, F64, 0, w.x64, w.to64, w.t64, m_out, RED_NONE, FIN_NONE));
-    DP_TRY(blas(c, OP_SUB64, n, F64, m_out, {&w.r64, &w.b64, &w.t64}, FIN_STORE));
-    DP_HIP(c, hipMemcpyAsync(sums, w.out_sums.p, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, c->stream));
-    DP_HIP(c, hipStreamSynchronize(c->stream));
-    std::vector<int> start(n, 0);
-    bool any_start = false;
-    for (int s = 0; s < n; ++s) {
-      if (!pend[s]) continue;
-      SlotHost& h = hs[s];
-      h.outer++;
-      h.hops += 2;
-      h.res2 = sums[4 * s];
-      if (!std::isfinite(h.res2)) {
-        h.done = 1;
-        h.status = DP_ERR_NONFINITE;
-      } else if (h.res2 <= r2 * h.eta2) {
-        h.done = 1;
-        h.status = DP_OK;
-      } else if (h.iters >= P.max_iter) {
-        h.done = 1;
-        h.status = DP_ERR_NOT_CONVERGED;
-      } else {
-        start[s] = 1;
-        any_start = true;
-        h.scale = std::sqrt(h.res2);
-        double need = 0.5 * P.r * std::sqrt(h.eta2 / h.res2);
-        double tol = prec == F64 ? need : (need > delta ? need : delta);
-        if (tol > 0.5) tol = 0.5;
-        h.tol2 = tol * tol;
-      }
-    }
-    if (!any_start) return DP_OK;
-    for (int s = 0; s < n; ++s) hscale[s] = start[s] ? 1.0 / hs[s].scale : 0.0;
-    DP_HIP(c, hipMemcpyAsync(w.slot_scale.p, hscale, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
-    for (int s = 0; s < n; ++s) outer[s] = start[s];
-    DP_TRY(upload_mask(c, w.mask_outer, outer, 1));
-    DP_TRY(blas(c, OP_SCALE_COPY, n, prec, m_out, {&w.r, &w.r64}));
-    DP_TRY(blas(c, OP_BICG_INIT, n, prec, m_out, {&w.rh, &w.r, &w.p, &w.v, &w.x}, FIN_BICG_INIT));
-    if (cgnr) {
-      DP_TRY(schur(c, n, prec, 1, w.r, w.to, w.s, m_out, RED_NORM, FIN_CG_INIT));
-      DP_TRY(blas(c, OP_COPY, n, prec, m_out, {&w.p, &w.s}));
-    }
-    for (int s = 0; s < n; ++s)
-      if (start[s]) {
-        hs[s].in_inner = 1;
-        hs[s].has_inner = 1;
-        hs[s].hops += cgnr ? 2 : 0;  // z = Mhat'^+ r
-        inner[s] = 1;
-      }
-    DP_TRY(upload_mask(c, w.mask_inner, inner, 2));
-    return DP_OK;
-  };
-
-  DP_TRY(outer_step(all));
-  while (true) {
-    bool any = false;
-    for (int s = 0; s < n; ++s) any |= hs[s].in_inner != 0;
-    if (!any) break;
-    if (!cgnr) {
-      DP_TRY(blas(c, OP_BICG_P, n, prec, m_in, {&w.p, &w.r, &w.v}));
-      DP_TRY(schur(c, n, prec, 0, w.p, w.to, w.v, m_in, RED_DOT_EXT, FIN_BICG_ALPHA, &w.rh));
-      DP_TRY(blas(c, OP_BICG_S, n, prec, m_in, {&w.s, &w.r, &w.v}));
-      DP_TRY(schur(c, n, prec, 0, w.s, w.to, w.t, m_in, RED_TS, FIN_BICG_OMEGA));
-      DP_TRY(blas(c, OP_BICG_XR, n, prec, m_in, {&w.x, &w.p, &w.s, &w.r, &w.t, &w.rh}, FIN_BICG_RHO));
-    } else {
-      DP_TRY(schur(c, n, prec, 0, w.p, w.to, w.v, m_in, RED_NORM, FIN_CG_ALPHA));
-      DP_TRY(blas(c, OP_CG_XR, n, prec, m_in, {&w.x, &w.p, &w.r, &w.v}, FIN_RR));
-      DP_TRY(schur(c, n, prec, 1, w.r, w.to, w.s, m_in, RED_NORM, FIN_CG_BETA));
-      DP_TRY(blas(c, OP_CG_P, n, prec, m_in, {&w.p, &w.s}));
-    }
-    DP_HIP(c, hipMemcpyAsync(hsc, w.sc.p, sizeof(SlotScalars) * n, hipMemcpyDeviceToHost, c->stream));
-    DP_HIP(c, hipStreamSynchronize(c->stream));
-    std::vector<int> pend(n, 0);
-    bool any_pend = false;
-    for (int s = 0; s < n; ++s) {
-      SlotHost& h = hs[s];
-      if (!h.in_inner) continue;
-      h.iters++;
-      h.hops += 4;
-      const double rr = hsc[s].rr;
-      bool leave = false;
-      if (!std::isfinite(rr) || rr <= h.tol2 || h.iters >= P.max_iter) leave = true;
-      if (!cgnr && hsc[s].breakdown) {
-        leave = true;
-        h.restarts++;
-      }
-      if (leave) {
-        h.in_inner = 0;
-        inner[s] = 0;
-        pend[s] = 1;
-        any_pend = true;
-      }
-    }
-    if (any_pend) {
-      DP_TRY(upload_mask(c, w.mask_inner, inner, 2));
-      DP_TRY(outer_step(pend));
-    }
-  }
-
-  // odd sites S'_o = A_oo^-1 (eta'_o - H_oe S'_e), restoration and C_PP
-  DP_TRY(hop(c, n, F64, 1, 0, EPI_INV_SUB, 0.0, w.x64, w.to64, &w.eta_o, m_all));
-  if (S_dev)
-    DP_HIP(c, launch_spinor_export(g, w.x64.ref(), w.to64.ref(), n, w.alpha.as<double>(), S_dev, 2L * g.Vh * 12,
-                                   c->stream));
-  int rc = DP_OK;
-  if (cpp_out) {
-    DP_HIP(c, launch_cpp(g, w.x64.ref(), w.to64.ref(), n, w.alpha.as<double>(), w.x0src.as<int>(),
-                         w.cpp.as<double>(), c->stream));
-    std::vector<double> per(static_cast<size_t>(n) * g.T);
-    DP_HIP(c, hipMemcpyAsync(per.data(), w.cpp.p, sizeof(double) * g.T * n, hipMemcpyDeviceToHost, c->stream));
-    DP_HIP(c, hipStreamSynchronize(c->stream));
-    const int grp = P.ncols_group > 0 ? P.ncols_group : 1;
-    for (int k = 0; k < n / grp; ++k)
-      for (int t = 0; t < g.T; ++t) {
-        double acc = 0.0;
-        for (int j = 0; j < grp; ++j) acc += per[(size_t)(k * grp + j) * g.T + t];
-        cpp_out[(size_t)k * g.T + t] = acc;
-      }
-  }
-  DP_HIP(c, hipStreamSynchronize(c->stream));
-  DP_TRY(timing_harvest(c));
-  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-  for (int s = 0; s < n; ++s) {
-    if (hs[s].status != DP_OK && rc == DP_OK) rc = hs[s].status;
-    if (info) {
-      info[s].status = hs[s].status;
-      info[s].iters = hs[s].iters;
-      info[s].outer = hs[s].outer;
-      info[s].hop_calls = hs[s].hops;
-      info[s].restarts = hs[s].restarts;
-      info[s].true_res = hs[s].eta2 > 0 ? std::sqrt(hs[s].res2 / hs[s].eta2) : 0.0;
-      info[s].seconds = secs;
-    }
-  }
-  if (rc != DP_OK) {
-    if (rc == DP_ERR_NOT_CONVERGED) c->err = "a right-hand side reached max_iter before the residue r";
-    if (rc == DP_ERR_NONFINITE) c->err = "a residual became NaN or Inf";
-  }
-  return rc;
-}
-
-int validate_params(dp_ctx* c, int nrhs, const dp_params* p) {
-  if (!p) return fail(c, DP_ERR_INVALID_ARG, "params is NULL");
-  if (nrhs <= 0) return fail(c, DP_ERR_INVALID_ARG, "nrhs must be positive");
-  if (!(p->r > 0) || !std::isfinite(p->r)) return fail(c, DP_ERR_INVALID_ARG, "r must be positive");
-  if (p->solver != DP_SOLVER_BICGSTAB && p->solver != DP_SOLVER_CGNR)
-    return fail(c, DP_ERR_INVALID_ARG, "unknown solver");
-  if (p->precision < DP_PREC_F64 || p->precision > DP_PREC_F16) return fail(c, DP_ERR_INVALID_ARG, "unknown precision");
-  if (p->max_iter <= 0) return fail(c, DP_ERR_INVALID_ARG, "max_iter must be positive");
-  if (p->delta < 0 || p->delta >= 1) return fail(c, DP_ERR_INVALID_ARG, "delta must be in [0, 1)");
-  if (p->x0_src < 0 || p->x0_src >= c->g.T) return fail(c, DP_ERR_INVALID_ARG, "x0_src outside [0, T)");
-  if (p->ncols_group < 0 || (p->ncols_group > 0 && nrhs % p->ncols_group != 0))
-    return fail(c, DP_ERR_INVALID_ARG, "nrhs must be a multiple of ncols_group");
-  return DP_OK;
-}
-
 // Udev == nullptr sets unit links
 int set_gauge_common(dp_ctx* c, const double2* Udev, hipStream_t st) {
+  DP_TRY(drop_masses(c));
   const Geom& g = c->g;
   for (int prec = 0; prec < 3; ++prec) {
     for (int p = 0; p < 2; ++p) DP_HIP(c, c->U[prec][p].reserve((size_t)g.Vh * link_site_bytes(prec)));
@@ -681,7 +424,6 @@ int set_gauge_common(dp_ctx* c, const double2* Udev, hipStream_t st) {
     c->have_U[prec] = true;
   }
   DP_HIP(c, hipStreamSynchronize(st));
-  drop_masses(c);
   c->clover_kind = 0;
   c->csw = 0.0;
   return clover_zero(c);
@@ -722,12 +464,7 @@ int dp_create(const int dims[4], int bc_t, int device, dp_ctx** out) {
     return DP_ERR_DEVICE;
   }
   c->alpha.assign(g.T, 1.0);
-  int rc = clover_zero(c);
-  if (rc != DP_OK) {
-    delete c;
-    return rc;
-  }
-  rc = set_gauge_common(c, nullptr, c->stream);  // unit links
+  int rc = set_gauge_common(c, nullptr, c->stream);  // unit links, no clover
   if (rc != DP_OK) {
     delete c;
     return rc;
@@ -740,6 +477,10 @@ void dp_destroy(dp_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  if (c->solve_batch) {
+    dp_batch_close(c->solve_batch);
+    c->solve_batch = nullptr;
+  }
   delete c;
 }
 
@@ -759,8 +500,7 @@ int dp_set_gauge(dp_ctx* c, const double* U) {
 int dp_set_gauge_dev(dp_ctx* c, const void* U, void* stream) {
   if (!c || !U) return fail(c, DP_ERR_INVALID_ARG, "null argument");
   DP_HIP(c, hipSetDevice(c->device));
-  hipStream_t st = stream ? (hipStream_t)stream : c->stream;
-  DP_HIP(c, hipStreamSynchronize(st));
+  if (stream) DP_HIP(c, hipStreamSynchronize((hipStream_t)stream));
   return set_gauge_common(c, static_cast<const double2*>(U), c->stream);
 }
 
@@ -768,7 +508,7 @@ int dp_set_clover(dp_ctx* c, double csw) {
   if (!c || !std::isfinite(csw)) return fail(c, DP_ERR_INVALID_ARG, "bad argument");
   DP_HIP(c, hipSetDevice(c->device));
   DP_TRY(check_state(c));
-  drop_masses(c);
+  DP_TRY(drop_masses(c));
   if (csw == 0.0) {
     DP_TRY(clover_zero(c));
     c->clover_kind = 0;
@@ -787,6 +527,7 @@ int dp_set_clover(dp_ctx* c, double csw) {
 int dp_set_clover_field(dp_ctx* c, const double* Cf) {
   if (!c || !Cf) return fail(c, DP_ERR_INVALID_ARG, "null argument");
   DP_HIP(c, hipSetDevice(c->device));
+  DP_TRY(drop_masses(c));
   const size_t bytes = (size_t)2 * c->g.Vh * 144 * sizeof(double2);
   DP_HIP(c, c->scratch_aos.reserve(bytes));
   DP_HIP(c, hipMemcpyAsync(c->scratch_aos.p, Cf, bytes, hipMemcpyHostToDevice, c->stream));
@@ -798,7 +539,6 @@ int dp_set_clover_field(dp_ctx* c, const double* Cf) {
   DP_HIP(c, hipMemcpyAsync(&bad, c->bad_flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   DP_HIP(c, hipStreamSynchronize(c->stream));
   c->scratch_aos.release();
-  drop_masses(c);
   if (bad) {
     clover_zero(c);
     c->clover_kind = 0;
@@ -841,16 +581,22 @@ int dp_apply(dp_ctx* c, const double* in, double* out, int flags) {
   DP_TRY(check_state(c));
   const int prec = (flags & DP_APPLY_F32) ? F32 : (flags & DP_APPLY_F16) ? F16 : F64;
   const int dag = (flags & DP_DAGGER) ? 1 : 0;
-  DP_TRY(ensure_ws(c, 1, prec));
+  Workspace& w = c->ws_apply;
+  DP_TRY(ensure_ws(c, w, 1, prec));
   MassEntry* me = nullptr;
   DP_TRY(mass_entry(c, c->M, &me));
-  std::vector<double> ones(c->g.T, 1.0);
-  DP_TRY(upload_slot_tables(c, 1, (flags & DP_PRECOND) ? c->alpha.data() : ones.data(), me, 0));
-  Workspace& w = c->ws;
   const Geom& g = c->g;
-  std::vector<int> one(1, 1);
-  DP_TRY(upload_mask(c, w.mask_all, one, 0));
-  const int* m = w.mask_all.as<int>();
+  {
+    std::vector<double> ones(g.T, 1.0), rt(4 * g.T);
+    ratio_tables(g.T, c->bc_t, (flags & DP_PRECOND) ? c->alpha.data() : ones.data(), rt.data());
+    DP_TRY(h2d(c, w.ratio.p, rt.data(), sizeof(double) * 4 * g.T));
+    const double m4 = 4.0 + c->M;
+    DP_TRY(h2d(c, w.m4.p, &m4, sizeof(double)));
+    const void* p3[3] = {me->a64.p, me->a32.p, me->a16.p};
+    for (int k = 0; k < 3; ++k) DP_TRY(h2d(c, w.ainv_ptr[k].p, &p3[k], sizeof(void*)));
+    const float* s16 = me->s16.as<float>();
+    DP_TRY(h2d(c, w.ainv_scale_ptr.p, &s16, sizeof(float*)));
+  }
   const size_t bytes = (size_t)2 * g.Vh * 12 * sizeof(double2);
   DP_HIP(c, c->scratch_aos.reserve(bytes));
   DP_HIP(c, hipMemcpyAsync(c->scratch_aos.p, in, bytes, hipMemcpyHostToDevice, c->stream));
@@ -862,28 +608,28 @@ int dp_apply(dp_ctx* c, const double* in, double* out, int flags) {
   const Field* oe = &w.b64;
   const Field* oo = &w.to64;
   if (prec != F64) {
-    double one_d = 1.0;
-    DP_TRY(h2d(c, w.slot_scale.p, &one_d, sizeof(double)));
-    DP_TRY(blas(c, OP_SCALE_COPY, 1, prec, m, {&w.r, &w.eta_e}));
-    DP_TRY(blas(c, OP_SCALE_COPY, 1, prec, m, {&w.s, &w.eta_o}));
+    const double one = 1.0;
+    DP_TRY(h2d(c, w.slot_scale.p, &one, sizeof(double)));
+    DP_TRY(blas(c, w, 0, 1, OP_SCALE_COPY, prec, nullptr, {&w.r, &w.eta_e}));
+    DP_TRY(blas(c, w, 0, 1, OP_SCALE_COPY, prec, nullptr, {&w.s, &w.eta_o}));
     ie = &w.r;
     io = &w.s;
     oe = &w.v;
     oo = &w.t;
   }
   if (flags & DP_HOP_ONLY) {
-    DP_TRY(hop(c, 1, prec, 0, dag, EPI_HOP, 0.0, *io, *oe, nullptr, m));
-    DP_TRY(hop(c, 1, prec, 1, dag, EPI_HOP, 0.0, *ie, *oo, nullptr, m));
+    DP_TRY(hop(c, w, 0, 1, prec, 0, dag, EPI_HOP, 0.0, *io, *oe, nullptr, nullptr));
+    DP_TRY(hop(c, w, 0, 1, prec, 1, dag, EPI_HOP, 0.0, *ie, *oo, nullptr, nullptr));
   } else if (flags & DP_APPLY_SCHUR) {
-    DP_TRY(schur(c, 1, prec, dag, *ie, w.to, *oe, m, RED_NONE, FIN_NONE));
-    DP_TRY(blas(c, OP_ZERO, 1, prec, m, {oo}));
+    DP_TRY(schur(c, w, 0, 1, prec, dag, *ie, w.to, *oe, nullptr, RED_NONE, FIN_NONE));
+    DP_TRY(blas(c, w, 0, 1, OP_ZERO, prec, nullptr, {oo}));
   } else {
-    DP_TRY(hop(c, 1, prec, 0, dag, EPI_DIAG, 1.0, *io, *oe, ie, m));
-    DP_TRY(hop(c, 1, prec, 1, dag, EPI_DIAG, 1.0, *ie, *oo, io, m));
+    DP_TRY(hop(c, w, 0, 1, prec, 0, dag, EPI_DIAG, 1.0, *io, *oe, ie, nullptr));
+    DP_TRY(hop(c, w, 0, 1, prec, 1, dag, EPI_DIAG, 1.0, *ie, *oo, io, nullptr));
   }
   if (prec != F64) {
-    DP_TRY(blas(c, OP_TO64, 1, prec, m, {&w.b64, oe}));
-    DP_TRY(blas(c, OP_TO64, 1, prec, m, {&w.to64, oo}));
+    DP_TRY(blas(c, w, 0, 1, OP_TO64, prec, nullptr, {&w.b64, oe}));
+    DP_TRY(blas(c, w, 0, 1, OP_TO64, prec, nullptr, {&w.to64, oo}));
   }
   DP_HIP(c, launch_spinor_export(g, w.b64.ref(), w.to64.ref(), 1, nullptr, c->scratch_aos.as<double2>(), 0,
                                  c->stream));
@@ -891,32 +637,6 @@ int dp_apply(dp_ctx* c, const double* in, double* out, int flags) {
   DP_HIP(c, hipStreamSynchronize(c->stream));
   DP_TRY(timing_harvest(c));
   return DP_OK;
-}
-
-int dp_solve(dp_ctx* c, const double* eta, int nrhs, const dp_params* p, double* S, double* cpp, dp_info* info) {
-  if (!c || !eta) return fail(c, DP_ERR_INVALID_ARG, "null argument");
-  DP_HIP(c, hipSetDevice(c->device));
-  DP_TRY(validate_params(c, nrhs, p));
-  DP_TRY(check_state(c));
-  const size_t bytes = (size_t)nrhs * 2 * c->g.Vh * 12 * sizeof(double2);
-  DP_HIP(c, c->scratch_aos.reserve(bytes));
-  DP_HIP(c, hipMemcpyAsync(c->scratch_aos.p, eta, bytes, hipMemcpyHostToDevice, c->stream));
-  int rc = run_solve(c, c->scratch_aos.as<double2>(), nrhs, *p, S ? c->scratch_aos.as<double2>() : nullptr, cpp, info);
-  if (S && (rc == DP_OK || rc == DP_ERR_NOT_CONVERGED)) {
-    DP_HIP(c, hipMemcpyAsync(S, c->scratch_aos.p, bytes, hipMemcpyDeviceToHost, c->stream));
-    DP_HIP(c, hipStreamSynchronize(c->stream));
-  }
-  return rc;
-}
-
-int dp_solve_dev(dp_ctx* c, const void* eta, int nrhs, const dp_params* p, void* S, double* cpp, dp_info* info,
-                 void* stream) {
-  if (!c || !eta) return fail(c, DP_ERR_INVALID_ARG, "null argument");
-  DP_HIP(c, hipSetDevice(c->device));
-  DP_TRY(validate_params(c, nrhs, p));
-  DP_TRY(check_state(c));
-  if (stream) DP_HIP(c, hipStreamSynchronize((hipStream_t)stream));
-  return run_solve(c, static_cast<const double2*>(eta), nrhs, *p, static_cast<double2*>(S), cpp, info);
 }
 
 int dp_set_timing(dp_ctx* c, int enable) {
@@ -960,12 +680,13 @@ long long dp_footprint_bytes(const int dims[4], int nrhs, int precision, int new
   }
   const long long Vh = V / 2;
   long long b = 0;
-  for (int p = 0; p < 3; ++p) b += 2 * Vh * (long long)link_site_bytes(p);      // links
-  for (int p = 0; p < 3; ++p) b += 2 * Vh * (long long)clover_site_bytes(p);    // clover
-  b += 2 * Vh * 4;                                                              // FP16 clover scales
+  for (int p = 0; p < 3; ++p) b += 2 * Vh * (long long)link_site_bytes(p);    // links
+  for (int p = 0; p < 3; ++p) b += 2 * Vh * (long long)clover_site_bytes(p);  // clover
+  b += 2 * Vh * 4;                                                            // FP16 clover scales
   const long long mass = Vh * (long long)(clover_site_bytes(0) + clover_site_bytes(1) + clover_site_bytes(2) + 4);
   b += new_masses * mass;
-  const long long f64 = Vh * 192, fin = Vh * (long long)(spinor_site_bytes(precision) + spinor_scale_bytes(precision));
+  const long long f64 = Vh * 192;
+  const long long fin = Vh * (long long)(spinor_site_bytes(precision) + spinor_scale_bytes(precision));
   const long long fx = Vh * (long long)spinor_site_bytes(precision == 2 ? 1 : precision);
   b += nrhs * (7 * f64 + 7 * fin + fx);
   return b;
