@@ -43,6 +43,7 @@ def test_batch_join_and_leave_matches_solo(precision):
                 slots = B.admit(torch.from_numpy(eta.reshape(q["cols"], -1)).cuda(), S_t, M=q["M"],
                                 alpha=profile(DIMS[0], q["a0"], q["x0"]), r=r, x0_src=q["x0"], tag=k)
                 q["S_t"] = S_t
+                q["slots"] = slots
                 return slots
             assert admit(0) is not None and admit(1) is not None
             assert admit(2) is None  # only 5 slots: the third request waits
@@ -64,8 +65,7 @@ def test_batch_join_and_leave_matches_solo(precision):
             alpha = profile(DIMS[0], q["a0"], q["x0"])
             S_b = q["S_t"].cpu().numpy().reshape((q["cols"],) + DIMS + (4, 3))
             eta = point_columns(DIMS, q["x0"], q["cols"])
-            cpp_b = sum(res["cpp"] for res in got[k])
-            cpp_s = 0
+            cpp_b = {q["slots"].index(res["slot"]): res["cpp"] for res in got[k]}
             # solo solves of the same columns on a fresh context
             with lattice(DIMS) as L2:
                 L2.set_gauge(U)
@@ -73,12 +73,11 @@ def test_batch_join_and_leave_matches_solo(precision):
                 for c in range(q["cols"]):
                     S1, cpp1, info1 = solo(L2, eta[c], q["M"], alpha, q["x0"], r, precision)
                     assert np.array_equal(S1, S_b[c]), (k, c)
-                    cpp_s = cpp_s + cpp1
+                    assert np.array_equal(cpp1, cpp_b[c]), (k, c)
                     # stopping rule recomputed by the oracle
                     a6 = alpha[:, None, None, None, None, None]
                     res = a6 * eta[c] - oracle.apply(U, C, q["M"], a6 * S_b[c], alpha=alpha)
                     assert np.linalg.norm(res) <= 1.0001 * r * np.linalg.norm(a6 * eta[c])
-            assert np.array_equal(cpp_b, cpp_s)
             log(f"  request {k}: iters {[res['info']['iters'] for res in got[k]]}")
 
 
