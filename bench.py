@@ -41,6 +41,9 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests in the served stream (0 skips the serving measurement)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the stream, 1/s")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md on sharding)",
@@ -139,6 +142,11 @@ def main():
                          f"{t_or:.1f} s"}
         log(f"  {t_or:.1f} s for one column on {cpu['cores']} threads")
 
+    serving = None
+    if args.serve_requests > 0:
+        L.close()
+        serving = serve_stream(args, cfg)
+
     out = {
         "metric": METRIC,
         "value": round(solves_per_s, 3),
@@ -166,9 +174,39 @@ def main():
                      "alg_bytes_per_launch": st["bytes"] / st["launches"],
                      "all_hop_kernels_GBps": round(all_hop_gbs, 1)},
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     L.close()
+
+
+def serve_stream(args, cfg3):
+    """The served stream: resident 16^3x32 and 24^3x48 fields, Poisson arrivals,
+    each request drawing M from {0.01, 0.05, 0.2, 0.5}, alpha0 from
+    {0, 0.1, 0.4} and 1-12 point-source columns at a random x0; batched solves
+    to r = 1e-10, first with the FP32 inner solver, then the FP64 one."""
+    import synth
+    from paper_1006_4028_amd.serve import Server, poisson_requests, summarize
+    cfg2 = synth.config("su3_16c32")
+    fields = {"16c32": (cfg2["dims"], synth.gauge_su3(cfg2["dims"], cfg2["eps"], cfg2["seed"]), cfg2["csw"]),
+              "24c48": (cfg3["dims"], synth.gauge_su3(cfg3["dims"], cfg3["eps"], cfg3["seed"]), cfg3["csw"])}
+    T_of = {k: v[0][0] for k, v in fields.items()}
+    out = {"workload": "16^3x32 + 24^3x48 resident, Poisson arrivals, M in {0.01,0.05,0.2,0.5}, "
+                       "alpha0 in {0,0.1,0.4} (exp of min(t,T-t)), 1-12 columns at random x0, r=1e-10",
+           "rate_per_s": args.serve_rate, "requests": args.serve_requests}
+    for prec in ("f32", "f64"):
+        log(f"served stream, {prec} inner: {args.serve_requests} requests at {args.serve_rate}/s")
+        reqs = poisson_requests(args.serve_requests, args.serve_rate, fields, T_of, seed=2024)
+        srv = Server(fields, nslots=24, precision=prec, r=1e-10, max_iter=20000, k=4)
+        try:
+            s = summarize(srv, srv.run(reqs))
+        finally:
+            srv.close()
+        log(f"  {s}")
+        out[prec] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in s.items()}
+    if out["f64"]["solves_per_s"] > 0:
+        out["mixed_over_fp64_solves_per_s"] = round(out["f32"]["solves_per_s"] / out["f64"]["solves_per_s"], 3)
+    return out
 
 
 if __name__ == "__main__":
