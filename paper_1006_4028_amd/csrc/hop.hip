@@ -21,6 +21,9 @@
 //
 // One thread per output site and group of up to four right-hand sides
 // ("slots"); the links of the site are loaded once for the group.
+#include <algorithm>
+#include <cstdlib>
+
 #include "dp_device.h"
 
 namespace dp {
@@ -268,6 +271,13 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st) {
   // epilogue already fills the register file with one
   int ns = a.nslots >= 4 ? 4 : a.nslots >= 2 ? 2 : 1;
   if (P == F64) ns = (EPI == EPI_DIAG || a.nslots < 2) ? 1 : 2;
+  // tuning knob: DP_HOP_NS in {1, 2, 4} overrides the slots per thread
+  static const int forced = [] {
+    const char* e = getenv("DP_HOP_NS");
+    const int v = e ? atoi(e) : 0;
+    return (v == 1 || v == 2 || v == 4) ? v : 0;
+  }();
+  if (forced) ns = std::min(forced, a.nslots >= 4 ? 4 : a.nslots >= 2 ? 2 : 1);
   const int ngroups = (a.nslots + ns - 1) / ns;
   const dim3 grid(ntiles * ngroups);
   switch (ns) {
