@@ -267,10 +267,11 @@ __global__ void __launch_bounds__(kBlock) hop_kernel(HopArgs a) {
 
 template <int P, int EPI, int RED>
 hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st) {
-  // slots per thread: four in the inner precisions; in FP64 the clover
-  // epilogue already fills the register file with one
-  int ns = a.nslots >= 4 ? 4 : a.nslots >= 2 ? 2 : 1;
-  if (P == F64) ns = (EPI == EPI_DIAG || a.nslots < 2) ? 1 : 2;
+  // slots per thread (measured on MI355X, 24^3x48 with 12 slots): two in
+  // FP32, one in FP16 (the L2 keeps more neighbour spinors), one for the FP64
+  // clover epilogue (it already fills the register file)
+  int ns = P == F32 ? (a.nslots >= 2 ? 2 : 1) : 1;
+  if (P == F64 && EPI != EPI_DIAG && a.nslots >= 2) ns = 2;
   // tuning knob: DP_HOP_NS in {1, 2, 4} overrides the slots per thread
   static const int forced = [] {
     const char* e = getenv("DP_HOP_NS");

@@ -148,3 +148,29 @@ def test_error_codes():
         assert info[0]["status"] == -4
     with pytest.raises(dp.DPError):
         dp.Lattice((4, 4, 3, 4))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("alpha0", [0.1, -0.1])
+def test_light_mass_cgnr_vs_oracle(precision, alpha0):
+    """The light-quark workload's solver (CG on the normal equations, FP16
+    storage with per-site scales for the inner solve) at M = 0.01 with the
+    symmetric exponential profile in both signs, on a small lattice."""
+    dims, M, r = (8, 4, 4, 6), 0.01, 1e-10
+    log(f"test_light_mass_cgnr_vs_oracle {precision} alpha0={alpha0}")
+    U = synth.gauge_su3(dims, 0.2, 3264)
+    C = oracle.clover(U, 1.6)
+    alpha = synth.alpha_exp_sym(dims[0], alpha0)
+    eta = synth.point_sources_12(dims, (0, 0, 0, 0), ncols=2)
+    S_or = np.stack([oracle.solve(U, C, M, eta[c], alpha=alpha, r=1e-13, solver="cgnr")[0] for c in range(2)])
+    with lattice(dims) as L:
+        L.set_gauge(U)
+        L.set_clover(1.6)
+        L.set_mass(M)
+        L.set_alpha(alpha)
+        S, cpp, info = L.solve(eta, r=r, solver="cgnr", precision=precision, max_iter=50000)
+    log("  iters", [i["iters"] for i in info], "outer", [i["outer"] for i in info])
+    for k in range(2):
+        assert info[k]["status"] == 0
+        assert true_residual(U, C, M, alpha, S[k], eta[k]) <= 1.0001 * r
+        assert np.abs(cpp[k] / oracle.cpp(S_or[k]) - 1).max() < 1e-7
