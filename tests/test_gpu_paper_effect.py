@@ -36,8 +36,9 @@ def test_loose_residue_far_timeslices(precision):
     for k in range(0, dims[0], 4):
         log(f"  {k:2d}  {abs(exact[k]):.3e}  {e_plain[k]:.3e}      {e_prec[k]:.3e}")
     assert far.any()
-    # unpreconditioned: fine near the source, wrong where |C| < r^2
+    # unpreconditioned: fine near the source, wrong by percents where |C| nears r^2
     assert e_plain[t < 6].max() < 1e-3
-    assert e_plain[far].max() > 1e-1
-    # preconditioned at the same residue: right everywhere
-    assert e_prec.max() < 1e-3
+    assert e_plain[far].max() > 1e-2
+    # preconditioned at the same residue: right everywhere, by orders of magnitude more
+    assert e_prec.max() < 1e-4
+    assert e_prec[far].max() < 1e-3 * e_plain[far].max()
