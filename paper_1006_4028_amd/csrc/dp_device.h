@@ -434,9 +434,10 @@ __device__ inline void block_reduce_store(const ReduceRef& red, int nv, double (
   __syncthreads();
   if (threadIdx.x == 0) {
     double* part = red.partials + ((long)slot * nblocks + block) * 4;
+    const int nw = blockDim.x >> 6;  // blocks of 64 or kBlock threads
     for (int k = 0; k < nv; ++k) {
       double t = 0.0;
-      for (int w = 0; w < kBlock / 64; ++w) t += lds[k][w];
+      for (int w = 0; w < nw; ++w) t += lds[k][w];
       part[k] = t;
     }
   }

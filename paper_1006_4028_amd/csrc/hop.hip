@@ -206,17 +206,13 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
   }
 }
 
-// Grid: one block per (tile of kBlock sites, group of NS slots); the blocks
-// of each XCD cover a contiguous range of tiles with all slot groups of a
-// tile next to each other, so the groups of a tile share its links in L2.
+// The work of one thread: the hop for output site i (if valid) and the active
+// slots of its group, the epilogue, and its share of the fused reductions
+// (stored as the partial `part` of `nparts` per slot).
 template <int P, int EPI, int RED, int NS>
-__global__ void __launch_bounds__(kBlock) hop_kernel(HopArgs a) {
+__device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool valid, int part, int nparts) {
   using R = typename Tr<P>::R;
   const Geom& g = a.g;
-  const int ngroups = (a.nslots + NS - 1) / NS;
-  const int f = xcd_tile(blockIdx.x, gridDim.x);
-  const int tile = f / ngroups, grp = f - tile * ngroups;
-  const int ntiles = gridDim.x / ngroups;
   // active slots of the group (uniform over the block)
   int sl[NS];
   bool on[NS];
@@ -229,11 +225,10 @@ __global__ void __launch_bounds__(kBlock) hop_kernel(HopArgs a) {
     any = any || on[k];
   }
   if (!any) return;
-  const int i = tile * kBlock + threadIdx.x;
   double red[NS][4];
 #pragma unroll
   for (int k = 0; k < NS; ++k) red[k][0] = red[k][1] = red[k][2] = red[k][3] = 0.0;
-  if (i < g.Vh) {
+  if (valid) {
     int x[4];
     eo_coords(g, a.p, i, x[0], x[1], x[2], x[3]);
     R cf[NS], cb[NS];
@@ -261,8 +256,55 @@ __global__ void __launch_bounds__(kBlock) hop_kernel(HopArgs a) {
     constexpr int nv = RED == RED_DOT_EXT ? 2 : RED == RED_TS ? 3 : 1;
 #pragma unroll
     for (int k = 0; k < NS; ++k)
-      if (on[k]) block_reduce_store(a.red, nv, red[k], sl[k], tile, ntiles);
+      if (on[k]) block_reduce_store(a.red, nv, red[k], sl[k], part, nparts);
   }
+}
+
+// Contiguous mapping: one block per (tile of kBlock consecutive sites, group
+// of NS slots); the blocks of each XCD cover a contiguous range of tiles with
+// all slot groups of a tile next to each other, so the groups share its links
+// in L2.
+template <int P, int EPI, int RED, int NS>
+__global__ void __launch_bounds__(kBlock) hop_kernel(HopArgs a) {
+  const int ngroups = (a.nslots + NS - 1) / NS;
+  const int f = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = f / ngroups, grp = f - tile * ngroups;
+  const int i = tile * kBlock + threadIdx.x;
+  site_work<P, EPI, RED, NS>(a, grp, i, i < a.g.Vh, tile, gridDim.x / ngroups);
+}
+
+// Slab mapping: every XCD owns a fixed range of 64-site chunks of each
+// timeslice (a spatial slab) and sweeps the timeslices in order, one wave per
+// block; the x0 -+ 1 neighbour spinors of all slots then stay in that XCD's L2
+// (about 3 timeslices of its slab).  Block b runs on XCD b mod 8.
+struct SlabMap {
+  int nch, maxc, ngroups;
+};
+
+__device__ __forceinline__ int slab_lo(int nch, int xcd) { return (nch * xcd) >> 3; }
+
+template <int P, int EPI, int RED, int NS>
+__global__ void __launch_bounds__(64) hop_kernel_slab(HopArgs a, SlabMap m) {
+  const int xcd = blockIdx.x & 7;
+  int j = blockIdx.x >> 3;
+  const int grp = j % m.ngroups;
+  j /= m.ngroups;
+  const int cl = j % m.maxc, x0 = j / m.maxc;
+  const int chunk = slab_lo(m.nch, xcd) + cl;
+  const bool in_slab = chunk < slab_lo(m.nch, xcd + 1);
+  const int sp = chunk * 64 + threadIdx.x;
+  const bool valid = in_slab && sp < a.g.Vsh;
+  const int i = valid ? x0 * a.g.Vsh + sp : 0;
+  site_work<P, EPI, RED, NS>(a, grp, i, valid, (xcd * a.g.T + x0) * m.maxc + cl, 8 * a.g.T * m.maxc);
+}
+
+int hop_map_choice() {
+  // tuning knob: DP_HOP_MAP = 0 contiguous tiles, 1 slabs swept along x0
+  static const int v = [] {
+    const char* e = getenv("DP_HOP_MAP");
+    return e ? atoi(e) : -1;
+  }();
+  return v;
 }
 
 template <int P, int EPI, int RED>
@@ -280,16 +322,33 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st) {
   }();
   if (forced) ns = std::min(forced, a.nslots >= 4 ? 4 : a.nslots >= 2 ? 2 : 1);
   const int ngroups = (a.nslots + ns - 1) / ns;
-  const dim3 grid(ntiles * ngroups);
-  switch (ns) {
-    case 4: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 4>), grid, dim3(kBlock), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 2>), grid, dim3(kBlock), 0, st, a); break;
-    default: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 1>), grid, dim3(kBlock), 0, st, a); break;
+  const int map = hop_map_choice();
+  int nparts;
+  if (map == 1) {
+    SlabMap m;
+    m.nch = (a.g.Vsh + 63) / 64;
+    m.maxc = (m.nch + 7) / 8;
+    m.ngroups = ngroups;
+    nparts = 8 * a.g.T * m.maxc;
+    const dim3 grid(nparts * ngroups);
+    switch (ns) {
+      case 4: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 4>), grid, dim3(64), 0, st, a, m); break;
+      case 2: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 2>), grid, dim3(64), 0, st, a, m); break;
+      default: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 1>), grid, dim3(64), 0, st, a, m); break;
+    }
+  } else {
+    nparts = ntiles;
+    const dim3 grid(ntiles * ngroups);
+    switch (ns) {
+      case 4: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 4>), grid, dim3(kBlock), 0, st, a); break;
+      case 2: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 2>), grid, dim3(kBlock), 0, st, a); break;
+      default: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 1>), grid, dim3(kBlock), 0, st, a); break;
+    }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || RED == RED_NONE) return e;
   constexpr int nv = RED == RED_DOT_EXT ? 2 : RED == RED_TS ? 3 : 1;
-  return launch_finalize(a.red, nv, ntiles, a.nslots, a.slots.mask, st);
+  return launch_finalize(a.red, nv, nparts, a.nslots, a.slots.mask, st);
 }
 
 template <int P>
@@ -317,7 +376,10 @@ hipError_t launch_epi(const HopArgs& a, int ntiles, hipStream_t st) {
 
 int reduction_blocks(const Geom& g) { return (g.Vh + kBlock - 1) / kBlock; }
 
-int hop_blocks(const Geom& g) { return reduction_blocks(g); }
+int hop_blocks(const Geom& g) {
+  const int nch = (g.Vsh + 63) / 64;
+  return std::max(reduction_blocks(g), 8 * g.T * ((nch + 7) / 8));
+}
 
 hipError_t launch_hop(const HopArgs& a, hipStream_t st) {
   if (a.nslots <= 0 || a.g.Vh <= 0) return hipErrorInvalidValue;
