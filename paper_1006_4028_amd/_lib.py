@@ -72,6 +72,14 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1006_4028_amd.build` "
                           "(hipcc, gfx950); there is no CPU fallback")
+    # torch bundles its own HIP runtime under the same soname as the system one
+    # libdp.so links; whichever loads first serves the whole process, and torch
+    # cannot initialise the GPU on a runtime newer than its own.  Loading torch
+    # first makes both use torch's runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
     L.dp_create.argtypes = [ip, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
