@@ -322,7 +322,9 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st) {
   }();
   if (forced) ns = std::min(forced, a.nslots >= 4 ? 4 : a.nslots >= 2 ? 2 : 1);
   const int ngroups = (a.nslots + ns - 1) / ns;
-  const int map = hop_map_choice();
+  // measured on MI355X (24^3x48): slabs win with several slots (x0 neighbours
+  // of all slots stay in the XCD's L2), contiguous tiles with one
+  const int map = hop_map_choice() >= 0 ? hop_map_choice() : (a.nslots >= 2 ? 1 : 0);
   int nparts;
   if (map == 1) {
     SlabMap m;
