@@ -26,6 +26,91 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Dslash HBM GB/s (% roofline); solves/s + p99 latency, mixed vs FP64 at r=1e-11"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hop_f32_diag_24c48_12rhs.json")
+KERNEL_SOURCES = ["paper_1006_4028_amd/csrc/hop.hip", "paper_1006_4028_amd/csrc/dp_device.h",
+                  "paper_1006_4028_amd/csrc/dp_common.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    record, if it was taken on the current kernel sources (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def pmc_probe():
+    """Run under rocprofv3 --pmc: a 1 GiB device copy (the counters' scale),
+    then one step of the timed configuration (12 columns, FP32 inner)."""
+    import torch
+    x = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    import paper_1006_4028_amd as dp
+    import synth
+    cfg = synth.config("su3_24c48")
+    dims = cfg["dims"]
+    U = synth.gauge_su3(dims, cfg["eps"], cfg["seed"])
+    eta = synth.point_sources_12(dims, (0, 0, 0, 0), 12)
+    e_t = torch.from_numpy(eta.reshape(12, -1)).cuda()
+    L = dp.Lattice(dims)
+    L.set_gauge(U)
+    L.set_clover(cfg["csw"])
+    L.set_mass(cfg["masses"][0])
+    L.set_alpha(synth.alpha_table(cfg["profile"], dims[0], cfg["alpha0s"][-1]))
+    L.solve_dev(e_t, None, r=cfg["r"], precision="f32", ncols_group=12)
+    torch.cuda.synchronize()
+    L.close()
+
+
+def pmc_summary(fetch_csv, write_csv, command):
+    """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the dominant kernel
+    (the FP32 even-site hop with the clover epilogue, full 12-slot launches) by
+    what the same counters read for the 1 GiB copy, and record them."""
+    import csv
+
+    def rows(path):
+        return list(csv.DictReader(open(path)))
+
+    def is_copy(r):
+        return "copyBuffer" in r["Kernel_Name"] or "copy" in r["Kernel_Name"].lower() and "dp::" not in r["Kernel_Name"]
+
+    def is_hop(r):
+        return "hop_kernel" in r["Kernel_Name"] and "<1, 2, 1," in r["Kernel_Name"] or \
+            "hop_kernel" in r["Kernel_Name"] and "<1, 2, 2," in r["Kernel_Name"]
+
+    out = {}
+    for key, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rs = rows(path)
+        copy = max(float(r["Counter_Value"]) for r in rs if is_copy(r))
+        hop = [float(r["Counter_Value"]) for r in rs if is_hop(r)]
+        full = [v for v in hop if v > 0.5 * max(hop)]  # launches with every slot active
+        out[key + "_kib_per_launch"] = sum(full) / len(full)
+        out[key + "_copy_kib"] = copy
+        out[key + "_scale"] = (1 << 20) / copy  # 1 GiB = 2^20 KiB moved by the copy
+        out[key + "_launches"] = len(full)
+    hbm = 1024 * (out["fetch_kib_per_launch"] * out["fetch_scale"] + out["write_kib_per_launch"] * out["write_scale"])
+    rec = {"kernel": "hop_f32_diag (hop_kernel_slab<1, 2, 1|2, 2>), 24^3x48, 12 slots", "command": command,
+           "source_sha256": kernel_source_hash(), "hbm_bytes_per_launch": hbm, **out}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
 
 
 def log(*a):
@@ -44,7 +129,14 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=40,
                     help="requests in the served stream (0 skips the serving measurement)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the stream, 1/s")
+    ap.add_argument("--pmc-probe", action="store_true", help="run the counter probe (under rocprofv3 --pmc)")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
+                    help="write the traffic record of the dominant kernel from two counter runs")
     args = ap.parse_args()
+    if args.pmc_probe:
+        return pmc_probe()
+    if args.pmc_summary:
+        return pmc_summary(*args.pmc_summary)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md on sharding)",
               file=sys.stderr)
@@ -142,6 +234,7 @@ def main():
                          f"{t_or:.1f} s"}
         log(f"  {t_or:.1f} s for one column on {cpu['cores']} threads")
 
+    traffic = measured_traffic()
     serving = None
     if args.serve_requests > 0:
         L.close()
@@ -169,7 +262,7 @@ def main():
         "fp64": fp64,
         "speedup_vs_fp64": round(solves_per_s / fp64["value"], 3) if fp64 else None,
         "roofline": {"bound": "hbm", "kernel": name, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "avg_launch_us": round(1e3 * avg_ms, 2),
                      "alg_bytes_per_launch": st["bytes"] / st["launches"],
                      "all_hop_kernels_GBps": round(all_hop_gbs, 1)},
