@@ -78,6 +78,81 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return xcd * q + (xcd < r ? xcd : r) + k;
 }
 
+// ------------------------------------------------------------ streamed access
+//
+// Loads and stores of data touched once per launch (the epilogue's inputs and
+// the output) can be marked non-temporal, so that they do not displace the
+// neighbour spinors and links that other sites of the sweep read again.
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ float4 vld(const float4* p) {
+  if constexpr (NT) {
+    const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ double2 vld(const double2* p) {
+  if constexpr (NT) {
+    const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+    return make_double2(v.x, v.y);
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ uint4 vld(const uint4* p) {
+  if constexpr (NT) {
+    const u4v v = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ float vld(const float* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void vst(float4* p, float4 v) {
+  if constexpr (NT) {
+    const f4v w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<f4v*>(p));
+  } else {
+    *p = v;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void vst(double2* p, double2 v) {
+  if constexpr (NT) {
+    const d2v w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<d2v*>(p));
+  } else {
+    *p = v;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void vst(uint4* p, uint4 v) {
+  if constexpr (NT) {
+    const u4v w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<u4v*>(p));
+  } else {
+    *p = v;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void vst(float* p, float v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // ------------------------------------------------------------ spinors
 
 template <int P>
@@ -85,42 +160,42 @@ struct SpinorIO;
 
 template <>
 struct SpinorIO<F64> {
-  template <typename R>
+  template <bool NT = false, typename R>
   __device__ static __forceinline__ void load(const SpinorRef& f, int slot, int i, int Vh, cx<R> (&s)[12]) {
     const double2* b = static_cast<const double2*>(f.data) + (long)slot * f.slot_stride;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      const double2 v = b[(long)c * Vh + i];
+      const double2 v = vld<NT>(b + (long)c * Vh + i);
       s[c] = cx<R>{(R)v.x, (R)v.y};
     }
   }
-  template <typename R>
+  template <bool NT = false, typename R>
   __device__ static __forceinline__ void store(const SpinorRef& f, int slot, int i, int Vh, const cx<R> (&s)[12]) {
     double2* b = static_cast<double2*>(f.data) + (long)slot * f.slot_stride;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) b[(long)c * Vh + i] = make_double2((double)s[c].x, (double)s[c].y);
+    for (int c = 0; c < 12; ++c) vst<NT>(b + (long)c * Vh + i, make_double2((double)s[c].x, (double)s[c].y));
   }
 };
 
 template <>
 struct SpinorIO<F32> {
-  template <typename R>
+  template <bool NT = false, typename R>
   __device__ static __forceinline__ void load(const SpinorRef& f, int slot, int i, int Vh, cx<R> (&s)[12]) {
     const float4* b = static_cast<const float4*>(f.data) + (long)slot * f.slot_stride;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const float4 v = b[(long)k * Vh + i];
+      const float4 v = vld<NT>(b + (long)k * Vh + i);
       s[2 * k] = cx<R>{(R)v.x, (R)v.y};
       s[2 * k + 1] = cx<R>{(R)v.z, (R)v.w};
     }
   }
-  template <typename R>
+  template <bool NT = false, typename R>
   __device__ static __forceinline__ void store(const SpinorRef& f, int slot, int i, int Vh, const cx<R> (&s)[12]) {
     float4* b = static_cast<float4*>(f.data) + (long)slot * f.slot_stride;
 #pragma unroll
     for (int k = 0; k < 6; ++k)
-      b[(long)k * Vh + i] = make_float4((float)s[2 * k].x, (float)s[2 * k].y, (float)s[2 * k + 1].x,
-                                        (float)s[2 * k + 1].y);
+      vst<NT>(b + (long)k * Vh + i, make_float4((float)s[2 * k].x, (float)s[2 * k].y, (float)s[2 * k + 1].x,
+                                               (float)s[2 * k + 1].y));
   }
 };
 
@@ -135,13 +210,13 @@ __device__ __forceinline__ unsigned f2h(float a, float b) {
 
 template <>
 struct SpinorIO<F16> {
-  template <typename R>
+  template <bool NT = false, typename R>
   __device__ static __forceinline__ void load(const SpinorRef& f, int slot, int i, int Vh, cx<R> (&s)[12]) {
     const uint4* b = static_cast<const uint4*>(f.data) + (long)slot * f.slot_stride;
-    const float sc = f.scale[(long)slot * f.scale_stride + i];
+    const float sc = vld<NT>(f.scale + (long)slot * f.scale_stride + i);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const uint4 v = b[(long)k * Vh + i];
+      const uint4 v = vld<NT>(b + (long)k * Vh + i);
       float2 a0 = h2f(v.x), a1 = h2f(v.y), a2 = h2f(v.z), a3 = h2f(v.w);
       s[4 * k + 0] = cx<R>{(R)(a0.x * sc), (R)(a0.y * sc)};
       s[4 * k + 1] = cx<R>{(R)(a1.x * sc), (R)(a1.y * sc)};
@@ -149,14 +224,21 @@ struct SpinorIO<F16> {
       s[4 * k + 3] = cx<R>{(R)(a3.x * sc), (R)(a3.y * sc)};
     }
   }
-  template <typename R>
+  template <bool NT = false, typename R>
   __device__ static __forceinline__ void store(const SpinorRef& f, int slot, int i, int Vh, const cx<R> (&s)[12]) {
     uint4* b = static_cast<uint4*>(f.data) + (long)slot * f.slot_stride;
     float m = 0.f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf((float)s[c].x), fabsf((float)s[c].y)));
+    // A site whose largest component is below the smallest normal float is
+    // stored as zero: 1/m would overflow to Inf (and 0 * Inf is NaN).  Such
+    // sites arise from rounding residues of cancellations, which shrink by
+    // about the FP32 epsilon at every application of the operator; the
+    // solvers' fields are normalised to O(1), so dropping them is exact to
+    // far below the FP16 resolution.
+    if (!(m >= 1.17549435e-38f)) m = 0.f;  // FLT_MIN
     const float inv = m > 0.f ? 1.0f / m : 0.f;
-    f.scale[(long)slot * f.scale_stride + i] = m;
+    vst<NT>(f.scale + (long)slot * f.scale_stride + i, m);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       uint4 v;
@@ -164,7 +246,7 @@ struct SpinorIO<F16> {
       v.y = f2h((float)s[4 * k + 1].x * inv, (float)s[4 * k + 1].y * inv);
       v.z = f2h((float)s[4 * k + 2].x * inv, (float)s[4 * k + 2].y * inv);
       v.w = f2h((float)s[4 * k + 3].x * inv, (float)s[4 * k + 3].y * inv);
-      b[(long)k * Vh + i] = v;
+      vst<NT>(b + (long)k * Vh + i, v);
     }
   }
 };

@@ -174,3 +174,29 @@ def test_light_mass_cgnr_vs_oracle(precision, alpha0):
         assert info[k]["status"] == 0
         assert true_residual(U, C, M, alpha, S[k], eta[k]) <= 1.0001 * r
         assert np.abs(cpp[k] / oracle.cpp(S_or[k]) - 1).max() < 1e-7
+
+
+@pytest.mark.parametrize("solver", ["cgnr", "bicgstab"])
+def test_fp16_point_source_long_support(solver):
+    """FP16 storage on a lattice large enough that a point source's Krylov
+    vectors keep sites holding only rounding residues of cancellations for
+    many iterations (32 x 16^3).  Those residues shrink by about the FP32
+    epsilon per operator application; the per-site scale of such a site must
+    not overflow when it falls below the smallest normal float (regression:
+    the CGNR solve went non-finite at its third iteration)."""
+    dims, M, r = (32, 16, 16, 16), 0.01, 1e-10
+    log(f"test_fp16_point_source_long_support {solver}")
+    U = synth.gauge_su3(dims, 0.2, 3264)
+    C = oracle.clover(U, 1.6)
+    alpha = synth.alpha_exp_sym(dims[0], 0.1)
+    eta = synth.point_sources_12(dims, (0, 0, 0, 0), ncols=1)
+    with lattice(dims) as L:
+        L.set_gauge(U)
+        L.set_clover(1.6)
+        L.set_mass(M)
+        L.set_alpha(alpha)
+        S, cpp, info = L.solve(eta, r=r, solver=solver, precision="f16", max_iter=20000)
+    log("  iters", info[0]["iters"], "outer", info[0]["outer"])
+    assert info[0]["status"] == 0
+    assert np.isfinite(S).all()
+    assert true_residual(U, C, M, alpha, S[0], eta[0]) <= 1.0001 * r
