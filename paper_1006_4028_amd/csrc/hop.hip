@@ -285,8 +285,18 @@ struct SlabMap {
 
 __device__ __forceinline__ int slab_lo(int nch, int xcd) { return (nch * xcd) >> 3; }
 
+// Minimum waves per SIMD the compiler must leave room for (register budget).
+// Measured on MI355X at 24^3x48 with 12 slots: 4 for FP16 with one slot per
+// thread is 2% faster; 3 for FP32 with two slots is 4% slower (a small spill,
+// and more waves in flight than the L2 holds the neighbour spinors for).
+template <int P, int NS>
+struct SlabWaves {
+  static constexpr int value = (P == F16 && NS == 1) ? 4 : 1;
+};
+
 template <int P, int EPI, int RED, int NS, bool NT>
-__global__ void __launch_bounds__(64) hop_kernel_slab(HopArgs a, SlabMap m) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SlabWaves<P, NS>::value)))
+hop_kernel_slab(HopArgs a, SlabMap m) {
   const int xcd = blockIdx.x & 7;
   int j = blockIdx.x >> 3;
   const int grp = j % m.ngroups;
