@@ -336,9 +336,11 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st) {
   }();
   if (forced) ns = std::min(forced, a.nslots >= 4 ? 4 : a.nslots >= 2 ? 2 : 1);
   const int ngroups = (a.nslots + ns - 1) / ns;
-  // measured on MI355X (24^3x48): slabs win with several slots (x0 neighbours
-  // of all slots stay in the XCD's L2), contiguous tiles with one
-  const int map = hop_map_choice() >= 0 ? hop_map_choice() : (a.nslots >= 2 ? 1 : 0);
+  // The mapping fixes how the fused reductions are partitioned, so it must not
+  // depend on the number of slots: a slot's result is then bitwise the same
+  // alone and in any batch.  Slabs (measured on MI355X at 24^3x48: 5% faster
+  // with 12 slots, 1-4% slower with one) are the default.
+  const int map = hop_map_choice() >= 0 ? hop_map_choice() : 1;
   // the slab kernel streams the epilogue inputs and the output past L2
   // (non-temporal; measured on MI355X: 3% faster at 24^3x48 with 12 slots,
   // FP32); tuning knob: DP_HOP_NT = 0 turns that off

@@ -9,7 +9,11 @@
 * 24^3 x 48 in the launch configuration bench.py times (12 columns, FP32
   inner): the oracle recomputes the true residual of sampled columns and
   their C_PP agree with the FP64 GPU solve per timeslice;
-* the full operator at 24^3 x 48 element by element against the oracle.
+* the full operator at 24^3 x 48 element by element against the oracle;
+* 32^3 x 64 at the light mass M = 0.01 (CG on the normal equations, FP16
+  storage, the symmetric exponential profile in both signs): the oracle
+  recomputes the true residual of sampled columns and their C_PP, and the
+  FP16 correlator agrees with the FP64 GPU solve per timeslice.
 """
 import os
 
@@ -106,3 +110,39 @@ def test_24c48_operator_element_by_element():
     ref = oracle.apply(U, C, 0.5, psi, alpha=alpha)
     assert max_rel(got, ref) < 1e-13
     assert np.linalg.norm(got32 - ref) / np.linalg.norm(ref) < 2e-6
+
+
+@pytest.mark.parametrize("alpha0", [0.1, -0.1])
+def test_32c64_light_mass_cgnr_fp16(alpha0):
+    cfg = synth.config("su3_32c64")
+    dims, M, r = cfg["dims"], cfg["masses"][0], cfg["r"]
+    log(f"test_32c64_light_mass_cgnr_fp16 alpha0={alpha0}")
+    U = synth.gauge_su3(dims, cfg["eps"], cfg["seed"])
+    C = oracle.clover(U, cfg["csw"])
+    alpha = synth.alpha_table(cfg["profile"], dims[0], alpha0)
+    eta = synth.point_sources_12(dims, (0, 0, 0, 0))[[0, 7]]
+    with lattice(dims) as L:
+        L.set_gauge(U)
+        L.set_clover(cfg["csw"])
+        L.set_mass(M)
+        L.set_alpha(alpha)
+        S, cpp16, info = L.solve(eta, r=r, solver="cgnr", precision="f16", max_iter=20000)
+        _, cpp64, info64 = L.solve(eta, r=r, solver="cgnr", precision="f64", max_iter=20000, want_S=False)
+    log(f"  iters FP16 {[i['iters'] for i in info]}, FP64 {[i['iters'] for i in info64]}")
+    a6 = alpha[:, None, None, None, None, None]
+    for k in range(2):
+        assert info[k]["status"] == 0 and info64[k]["status"] == 0
+        res = a6 * eta[k] - oracle.apply(U, C, M, a6 * S[k], alpha=alpha)
+        tr = np.linalg.norm(res) / np.linalg.norm(a6 * eta[k])
+        log(f"  column {k}: oracle true residual {tr:.3e}, GPU {info[k]['true_res']:.3e}")
+        assert tr <= 1.0001 * r
+        np.testing.assert_allclose(cpp16[k], oracle.cpp(S[k]), rtol=1e-12)
+        err = np.abs(cpp16[k] / cpp64[k] - 1).max()
+        # The stopping norm weighs timeslice t by alpha(t)^2, so a residual r
+        # bounds the error of S(t) relative to alpha(src)/alpha(t) times what
+        # it bounds without preconditioning: the paper's light-quark profile
+        # (alpha0 < 0 here, steepening the decay) gives up that factor at the
+        # far timeslices.
+        bound = 1e-8 * max(1.0, float(np.max(alpha[0] / alpha)))
+        log(f"  FP16 vs FP64 C_PP max per-timeslice rel err {err:.2e} (bound {bound:.2e})")
+        assert err <= bound
