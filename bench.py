@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=40,
                     help="requests in the served stream (0 skips the serving measurement)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the stream, 1/s")
+    ap.add_argument("--no-dslash", action="store_true", help="skip the operator (Dslash) benchmark")
+    ap.add_argument("--dslash-calls", type=int, default=100, help="timed operator calls per case")
     ap.add_argument("--pmc-probe", action="store_true", help="run the counter probe (under rocprofv3 --pmc)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="write the traffic record of the dominant kernel from two counter runs")
@@ -235,9 +237,10 @@ def main():
         log(f"  {t_or:.1f} s for one column on {cpu['cores']} threads")
 
     traffic = measured_traffic()
+    L.close()
+    dslash = None if args.no_dslash else dslash_bench(args)
     serving = None
     if args.serve_requests > 0:
-        L.close()
         serving = serve_stream(args, cfg)
 
     out = {
@@ -267,10 +270,74 @@ def main():
                      "alg_bytes_per_launch": st["bytes"] / st["launches"],
                      "all_hop_kernels_GBps": round(all_hop_gbs, 1)},
         "cpu_baseline": cpu,
+        "dslash": dslash,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
-    L.close()
+
+
+MALL_BYTES = 256 * 2 ** 20
+
+
+def dslash_bench(args):
+    """The even-site Schur operator (hop with A_oo^-1 on odd sites, then hop
+    with the clover diagonal on even sites) of the preconditioned system on
+    device-resident spinors, 24^3x48 (M = 0.5, cosh alpha0 = 0.4) and 32^3x64
+    (M = 0.01, symmetric exp alpha0 = 0.1), in FP64, FP32 and FP16 storage,
+    with 1 and 12 right-hand sides: 20 untimed calls, then per-launch HIP-event
+    durations of each hop kernel over the timed calls (median, p10, p90) and
+    the algorithmic HBM rate at the median.  Launches whose algorithmic bytes
+    fit the 256 MB MALL are flagged."""
+    import numpy as np
+    import torch
+
+    import paper_1006_4028_amd as dp
+    import synth
+
+    out = []
+    for name, a0 in (("su3_24c48", 0.4), ("su3_32c64", 0.1)):
+        cfg = synth.config(name)
+        dims = cfg["dims"]
+        log(f"operator benchmark {name}: {args.dslash_calls} timed calls per case")
+        U = synth.gauge_su3(dims, cfg["eps"], cfg["seed"])
+        L = dp.Lattice(dims)
+        L.set_gauge(U)
+        del U
+        L.set_clover(cfg["csw"])
+        L.set_mass(cfg["masses"][0])
+        L.set_alpha(synth.alpha_table(cfg["profile"], dims[0], a0))
+        V = int(np.prod(dims))
+        for nrhs in (1, 12):
+            gen = torch.Generator(device="cuda").manual_seed(nrhs)
+            x = torch.randn(nrhs, V * 12, dtype=torch.complex128, device="cuda", generator=gen)
+            y = torch.empty_like(x)
+            for prec in ("f64", "f32", "f16"):
+                for _ in range(20):
+                    L.apply_dev(x, y, precond=True, schur=True, precision=prec)
+                L.set_timing(True)
+                for _ in range(args.dslash_calls):
+                    L.apply_dev(x, y, precond=True, schur=True, precision=prec)
+                st = L.timing()
+                for k in sorted(st):
+                    if not k.startswith("hop_"):
+                        continue
+                    us = 1e3 * L.timing_samples(k)
+                    med = float(np.median(us))
+                    b = st[k]["bytes"] / st[k]["launches"]
+                    rec = {"workload": name, "precision": prec, "nrhs": nrhs, "kernel": k,
+                           "launches": st[k]["launches"], "median_us": round(med, 2),
+                           "p10_us": round(float(np.percentile(us, 10)), 2),
+                           "p90_us": round(float(np.percentile(us, 90)), 2),
+                           "alg_bytes": b, "GBps": round(b / (med * 1e-6) / 1e9, 1),
+                           "frac": round(b / (med * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                           "mall_resident": b < MALL_BYTES}
+                    out.append(rec)
+                    log(f"  {prec} nrhs={nrhs:2d} {k:14s} median {med:8.1f} us  {rec['GBps']:7.1f} GB/s "
+                        f"({100 * rec['frac']:.1f}%){'  MALL-resident' if rec['mall_resident'] else ''}")
+                L.set_timing(False)
+            del x, y
+        L.close()
+    return out
 
 
 def serve_stream(args, cfg3):

@@ -139,6 +139,15 @@ int dp_set_alpha(dp_ctx* ctx, const double* alpha);
  * operator uses the ctx's current gauge field, clover term, mass and alpha. */
 int dp_apply(dp_ctx* ctx, const double* in, double* out, int flags);
 
+/* dp_apply on nrhs spinors in device memory (host layout, nrhs consecutive
+ * full-lattice spinors, complex128): the same flags and operator, each
+ * right-hand side a slot of the multi-RHS kernels (the links are read once per
+ * launch for all of them).  in and out must not overlap.  Work already queued
+ * on hip_stream (nullable) completes first; the call returns when out is
+ * written.  The library's launch timing (dp_set_timing) covers these kernels,
+ * which makes this the operator benchmark. */
+int dp_apply_dev(dp_ctx* ctx, const void* in_dev, void* out_dev, int nrhs, int flags, void* hip_stream);
+
 /* Solve (D+M) S = eta for nrhs right-hand sides (host layout, nrhs spinors)
  * through the preconditioned system, to the residue p->r.
  *   S    : nullable; receives the nrhs restored solutions (host layout)
@@ -168,6 +177,10 @@ typedef struct {
 } dp_kernel_stat;
 int dp_set_timing(dp_ctx* ctx, int enable);
 int dp_get_timing(dp_ctx* ctx, dp_kernel_stat* out, int max, int* count);
+/* The event-to-event duration in ms of each timed launch of the kernel variant
+ * `name` (the first 65536 since dp_set_timing), in launch order: up to `max`
+ * copied to ms, *count set to the number available (0 for an unknown name). */
+int dp_get_timing_samples(dp_ctx* ctx, const char* name, float* ms, int max, int* count);
 
 /* ------------------------------------------------------------------ batches
  * A batch is a fixed set of nslots slots on one ctx, each solving one

@@ -105,6 +105,22 @@ class Lattice:
         self._check(self._L.dp_apply(self._h, _ptr(psi), _ptr(out), flags))
         return out
 
+    def apply_dev(self, in_t, out_t, precond=False, dagger=False, hop_only=False, schur=False, precision="f64"):
+        """dp_apply on torch CUDA tensors holding nrhs spinors in host layout
+        (complex128, contiguous); every right-hand side is a slot of the
+        multi-RHS kernels."""
+        import torch
+        assert in_t.is_cuda and out_t.is_cuda and in_t.is_contiguous() and out_t.is_contiguous()
+        assert in_t.dtype == torch.complex128 and out_t.dtype == torch.complex128
+        n = in_t.numel() // (self.V * 12)
+        assert n * self.V * 12 == in_t.numel() and out_t.numel() == in_t.numel()
+        flags = (L.DP_PRECOND if precond else 0) | (L.DP_DAGGER if dagger else 0)
+        flags |= (L.DP_HOP_ONLY if hop_only else 0) | (L.DP_APPLY_SCHUR if schur else 0)
+        flags |= {"f64": 0, "f32": L.DP_APPLY_F32, "f16": L.DP_APPLY_F16}[precision]
+        stream = torch.cuda.current_stream(in_t.device).cuda_stream
+        self._check(self._L.dp_apply_dev(self._h, ctypes.c_void_p(in_t.data_ptr()), ctypes.c_void_p(out_t.data_ptr()),
+                                         n, flags, ctypes.c_void_p(stream)))
+
     # ------------------------------------------------------------ timing
     def set_timing(self, enable=True):
         self._check(self._L.dp_set_timing(self._h, int(bool(enable))))
@@ -117,6 +133,14 @@ class Lattice:
         self._check(self._L.dp_get_timing(self._h, arr, n.value, ctypes.byref(n)))
         return {a.name.decode(): dict(launches=a.launches, ms=a.ms, bytes=a.bytes, flops=a.flops)
                 for a in arr[:n.value]}
+
+    def timing_samples(self, name):
+        """Per-launch durations (ms) of one timed kernel variant, in launch order."""
+        n = ctypes.c_int(0)
+        self._check(self._L.dp_get_timing_samples(self._h, name.encode(), None, 0, ctypes.byref(n)))
+        arr = (ctypes.c_float * max(n.value, 1))()
+        self._check(self._L.dp_get_timing_samples(self._h, name.encode(), arr, n.value, ctypes.byref(n)))
+        return np.array(arr[:n.value], dtype=np.float64)
 
     # ------------------------------------------------------------ solves
     @staticmethod

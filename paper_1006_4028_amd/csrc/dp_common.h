@@ -144,7 +144,10 @@ struct HopArgs {
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return hipSuccess or the launch error.
 
-hipError_t launch_hop(const HopArgs& a, hipStream_t stream);
+// The hop kernel alone; *nparts receives the number of per-slot block partials
+// it stored for a fused reduction (a.red.red != RED_NONE), which the caller
+// folds next with launch_finalize(a.red, nv, *nparts, ...).
+hipError_t launch_hop(const HopArgs& a, hipStream_t stream, int* nparts);
 
 // FP64 host-layout gauge field [site][mu][3][3] (device copy) -> SoA parity fields;
 // U_aos == nullptr gives unit links

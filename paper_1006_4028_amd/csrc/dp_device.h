@@ -160,6 +160,12 @@ struct SpinorIO;
 
 template <>
 struct SpinorIO<F64> {
+  // the components and the factor that multiplies them (1 without a scale)
+  template <typename R>
+  __device__ static __forceinline__ R load_unscaled(const SpinorRef& f, int slot, int i, int Vh, cx<R> (&s)[12]) {
+    load(f, slot, i, Vh, s);
+    return R(1);
+  }
   template <bool NT = false, typename R>
   __device__ static __forceinline__ void load(const SpinorRef& f, int slot, int i, int Vh, cx<R> (&s)[12]) {
     const double2* b = static_cast<const double2*>(f.data) + (long)slot * f.slot_stride;
@@ -179,6 +185,11 @@ struct SpinorIO<F64> {
 
 template <>
 struct SpinorIO<F32> {
+  template <typename R>
+  __device__ static __forceinline__ R load_unscaled(const SpinorRef& f, int slot, int i, int Vh, cx<R> (&s)[12]) {
+    load(f, slot, i, Vh, s);
+    return R(1);
+  }
   template <bool NT = false, typename R>
   __device__ static __forceinline__ void load(const SpinorRef& f, int slot, int i, int Vh, cx<R> (&s)[12]) {
     const float4* b = static_cast<const float4*>(f.data) + (long)slot * f.slot_stride;
@@ -210,6 +221,22 @@ __device__ __forceinline__ unsigned f2h(float a, float b) {
 
 template <>
 struct SpinorIO<F16> {
+  // the stored binary16 values (|v| <= 1) and the site's scale
+  template <typename R>
+  __device__ static __forceinline__ R load_unscaled(const SpinorRef& f, int slot, int i, int Vh, cx<R> (&s)[12]) {
+    const uint4* b = static_cast<const uint4*>(f.data) + (long)slot * f.slot_stride;
+    const float sc = f.scale[(long)slot * f.scale_stride + i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint4 v = b[(long)k * Vh + i];
+      const float2 a0 = h2f(v.x), a1 = h2f(v.y), a2 = h2f(v.z), a3 = h2f(v.w);
+      s[4 * k + 0] = cx<R>{(R)a0.x, (R)a0.y};
+      s[4 * k + 1] = cx<R>{(R)a1.x, (R)a1.y};
+      s[4 * k + 2] = cx<R>{(R)a2.x, (R)a2.y};
+      s[4 * k + 3] = cx<R>{(R)a3.x, (R)a3.y};
+    }
+    return (R)sc;
+  }
   template <bool NT = false, typename R>
   __device__ static __forceinline__ void load(const SpinorRef& f, int slot, int i, int Vh, cx<R> (&s)[12]) {
     const uint4* b = static_cast<const uint4*>(f.data) + (long)slot * f.slot_stride;

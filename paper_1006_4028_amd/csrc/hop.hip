@@ -19,7 +19,7 @@
 //   mu = k: h = u + s (i sigma_k) l,     lower = -s (i sigma_k) h
 // so only the two upper spins are multiplied by the link.
 //
-// One thread per output site and group of up to four right-hand sides
+// One thread per output site and group of one or two right-hand sides
 // ("slots"); the links of the site are loaded once for the group.
 #include <algorithm>
 #include <cstdlib>
@@ -35,8 +35,9 @@ struct Half {
   cx<R> h[2][3];
 };
 
-template <int MU, typename R>
-__device__ __forceinline__ void project(const cx<R> (&s)[12], R sg, Half<R>& o) {
+template <int MU, int S, typename R>
+__device__ __forceinline__ void project(const cx<R> (&s)[12], Half<R>& o) {
+  constexpr R sg = R(S);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const cx<R> u0 = s[a], u1 = s[3 + a], l0 = s[6 + a], l1 = s[9 + a];
@@ -57,8 +58,9 @@ __device__ __forceinline__ void project(const cx<R> (&s)[12], R sg, Half<R>& o) 
 }
 
 // acc += c * (1 - s gamma_mu)-reconstruction of the link-multiplied half spinor
-template <int MU, typename R>
-__device__ __forceinline__ void accumulate(cx<R> (&acc)[12], const Half<R>& w, R sg, R c) {
+template <int MU, int S, typename R>
+__device__ __forceinline__ void accumulate(cx<R> (&acc)[12], const Half<R>& w, R c) {
+  constexpr R sg = R(S);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const cx<R> w0 = c * w.h[0][a], w1 = c * w.h[1][a];
@@ -107,13 +109,17 @@ __device__ __forceinline__ void link_dag_mul(const cx<R> (&u)[9], const Half<R>&
 }
 
 // One direction mu, both hops, for the active slots of this thread's group.
-// The link is loaded once and used for every slot.
-template <int P, int MU, int NS>
+// The link is loaded once and used for every slot.  DAG selects the adjoint's
+// projectors at compile time (the signs then cost no arithmetic); an FP16
+// spinor's per-site scale multiplies the hop's coefficient instead of the 24
+// loaded components (the projection and the link product are linear).
+template <int P, int MU, int NS, bool DAG>
 __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], const bool (&on)[NS], int i,
                                         const int (&x)[4],
                                         const typename Tr<P>::R (&cf)[NS], const typename Tr<P>::R (&cb)[NS],
-                                        typename Tr<P>::R sg, cx<typename Tr<P>::R> (&acc)[NS][12]) {
+                                        cx<typename Tr<P>::R> (&acc)[NS][12]) {
   using R = typename Tr<P>::R;
+  constexpr int S = DAG ? -1 : 1;
   const Geom& g = a.g;
   const int L = MU == 0 ? g.T : MU == 1 ? g.L1 : MU == 2 ? g.L2 : g.L3;
   int y[4] = {x[0], x[1], x[2], x[3]};
@@ -126,10 +132,10 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     if (on[k]) {
-      SpinorIO<P>::load(a.in, sl[k], jf, g.Vh, psi);
-      project<MU>(psi, sg, h);
+      const R sc = SpinorIO<P>::load_unscaled(a.in, sl[k], jf, g.Vh, psi);
+      project<MU, S>(psi, h);
       link_mul(u, h, w);
-      accumulate<MU>(acc[k], w, sg, MU == 0 ? cf[k] : R(1));
+      accumulate<MU, S>(acc[k], w, MU == 0 ? cf[k] * sc : sc);
     }
   }
   // backward neighbour x - mu
@@ -139,10 +145,10 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     if (on[k]) {
-      SpinorIO<P>::load(a.in, sl[k], jb, g.Vh, psi);
-      project<MU>(psi, -sg, h);
+      const R sc = SpinorIO<P>::load_unscaled(a.in, sl[k], jb, g.Vh, psi);
+      project<MU, -S>(psi, h);
       link_dag_mul(u, h, w);
-      accumulate<MU>(acc[k], w, -sg, MU == 0 ? cb[k] : R(1));
+      accumulate<MU, -S>(acc[k], w, MU == 0 ? cb[k] * sc : sc);
     }
   }
 }
@@ -211,7 +217,7 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
 // The work of one thread: the hop for output site i (if valid) and the active
 // slots of its group, the epilogue, and its share of the fused reductions
 // (stored as the partial `part` of `nparts` per slot).
-template <int P, int EPI, int RED, int NS, bool NT>
+template <int P, int EPI, int RED, int NS, bool NT, bool DAG>
 __device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool valid, int part, int nparts) {
   using R = typename Tr<P>::R;
   const Geom& g = a.g;
@@ -237,19 +243,18 @@ __device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const double* rt = a.slots.ratio + (long)sl[k] * 4 * g.T;
-      cf[k] = (R)(a.dag ? rt[2 * g.T + x[0]] : rt[x[0]]);
-      cb[k] = (R)(a.dag ? rt[3 * g.T + x[0]] : rt[g.T + x[0]]);
+      cf[k] = (R)(DAG ? rt[2 * g.T + x[0]] : rt[x[0]]);
+      cb[k] = (R)(DAG ? rt[3 * g.T + x[0]] : rt[g.T + x[0]]);
     }
-    const R sg = a.dag ? R(-1) : R(1);
     cx<R> acc[NS][12];
 #pragma unroll
     for (int k = 0; k < NS; ++k)
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[k][c] = cx<R>{R(0), R(0)};
-    hop_dir<P, 0, NS>(a, sl, on, i, x, cf, cb, sg, acc);
-    hop_dir<P, 1, NS>(a, sl, on, i, x, cf, cb, sg, acc);
-    hop_dir<P, 2, NS>(a, sl, on, i, x, cf, cb, sg, acc);
-    hop_dir<P, 3, NS>(a, sl, on, i, x, cf, cb, sg, acc);
+    hop_dir<P, 0, NS, DAG>(a, sl, on, i, x, cf, cb, acc);
+    hop_dir<P, 1, NS, DAG>(a, sl, on, i, x, cf, cb, acc);
+    hop_dir<P, 2, NS, DAG>(a, sl, on, i, x, cf, cb, acc);
+    hop_dir<P, 3, NS, DAG>(a, sl, on, i, x, cf, cb, acc);
 #pragma unroll
     for (int k = 0; k < NS; ++k)
       if (on[k]) epilogue<P, EPI, RED, NT>(a, sl[k], i, acc[k], red[k]);
@@ -266,13 +271,13 @@ __device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool
 // of NS slots); the blocks of each XCD cover a contiguous range of tiles with
 // all slot groups of a tile next to each other, so the groups share its links
 // in L2.
-template <int P, int EPI, int RED, int NS>
+template <int P, int EPI, int RED, int NS, bool DAG>
 __global__ void __launch_bounds__(kBlock) hop_kernel(HopArgs a) {
   const int ngroups = (a.nslots + NS - 1) / NS;
   const int f = xcd_tile(blockIdx.x, gridDim.x);
   const int tile = f / ngroups, grp = f - tile * ngroups;
   const int i = tile * kBlock + threadIdx.x;
-  site_work<P, EPI, RED, NS, false>(a, grp, i, i < a.g.Vh, tile, gridDim.x / ngroups);
+  site_work<P, EPI, RED, NS, false, DAG>(a, grp, i, i < a.g.Vh, tile, gridDim.x / ngroups);
 }
 
 // Slab mapping: every XCD owns a fixed range of 64-site chunks of each
@@ -280,34 +285,41 @@ __global__ void __launch_bounds__(kBlock) hop_kernel(HopArgs a) {
 // block; the x0 -+ 1 neighbour spinors of all slots then stay in that XCD's L2
 // (about 3 timeslices of its slab).  Block b runs on XCD b mod 8.
 struct SlabMap {
-  int nch, maxc, ngroups;
+  int nch, maxc, ngroups, order;
 };
 
 __device__ __forceinline__ int slab_lo(int nch, int xcd) { return (nch * xcd) >> 3; }
 
-// Minimum waves per SIMD the compiler must leave room for (register budget).
-// Measured on MI355X at 24^3x48 with 12 slots: 4 for FP16 with one slot per
-// thread is 2% faster; 3 for FP32 with two slots is 4% slower (a small spill,
-// and more waves in flight than the L2 holds the neighbour spinors for).
-template <int P, int NS>
-struct SlabWaves {
-  static constexpr int value = (P == F16 && NS == 1) ? 4 : 1;
-};
-
-template <int P, int EPI, int RED, int NS, bool NT>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SlabWaves<P, NS>::value)))
-hop_kernel_slab(HopArgs a, SlabMap m) {
+// No minimum-waves hint: measured on MI355X at 24^3x48 with 12 slots, asking
+// for 3 waves per SIMD in FP32 (two slots per thread) or 4 in FP16 makes the
+// compiler spill and the kernels slower.
+template <int P, int EPI, int RED, int NS, bool NT, bool DAG>
+__global__ void __launch_bounds__(64) hop_kernel_slab(HopArgs a, SlabMap m) {
   const int xcd = blockIdx.x & 7;
   int j = blockIdx.x >> 3;
-  const int grp = j % m.ngroups;
-  j /= m.ngroups;
-  const int cl = j % m.maxc, x0 = j / m.maxc;
+  int grp, cl, x0;
+  if (m.order == 0) {  // slot groups of a chunk together, then chunks, then timeslices
+    grp = j % m.ngroups;
+    j /= m.ngroups;
+    cl = j % m.maxc;
+    x0 = j / m.maxc;
+  } else if (m.order == 1) {  // chunks, then slot groups, then timeslices
+    cl = j % m.maxc;
+    j /= m.maxc;
+    grp = j % m.ngroups;
+    x0 = j / m.ngroups;
+  } else {  // chunks, then timeslices, then slot groups
+    cl = j % m.maxc;
+    j /= m.maxc;
+    x0 = j % a.g.T;
+    grp = j / a.g.T;
+  }
   const int chunk = slab_lo(m.nch, xcd) + cl;
   const bool in_slab = chunk < slab_lo(m.nch, xcd + 1);
   const int sp = chunk * 64 + threadIdx.x;
   const bool valid = in_slab && sp < a.g.Vsh;
   const int i = valid ? x0 * a.g.Vsh + sp : 0;
-  site_work<P, EPI, RED, NS, NT>(a, grp, i, valid, (xcd * a.g.T + x0) * m.maxc + cl, 8 * a.g.T * m.maxc);
+  site_work<P, EPI, RED, NS, NT, DAG>(a, grp, i, valid, (xcd * a.g.T + x0) * m.maxc + cl, 8 * a.g.T * m.maxc);
 }
 
 int env_knob(const char* name, int dflt) {
@@ -321,20 +333,21 @@ int hop_map_choice() {
   return v;
 }
 
-template <int P, int EPI, int RED>
-hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st) {
+template <int P, int EPI, int RED, bool DAG>
+hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_out) {
   // slots per thread (measured on MI355X, 24^3x48 with 12 slots): two in
   // FP32, one in FP16 (the L2 keeps more neighbour spinors), one for the FP64
   // clover epilogue (it already fills the register file)
   int ns = P == F32 ? (a.nslots >= 2 ? 2 : 1) : 1;
   if (P == F64 && EPI != EPI_DIAG && a.nslots >= 2) ns = 2;
-  // tuning knob: DP_HOP_NS in {1, 2, 4} overrides the slots per thread
+  // tuning knob: DP_HOP_NS in {1, 2} overrides the slots per thread (4 was
+  // measured slower everywhere and is not built)
   static const int forced = [] {
     const char* e = getenv("DP_HOP_NS");
     const int v = e ? atoi(e) : 0;
-    return (v == 1 || v == 2 || v == 4) ? v : 0;
+    return (v == 1 || v == 2) ? v : 0;
   }();
-  if (forced) ns = std::min(forced, a.nslots >= 4 ? 4 : a.nslots >= 2 ? 2 : 1);
+  if (forced) ns = std::min(forced, a.nslots >= 2 ? 2 : 1);
   const int ngroups = (a.nslots + ns - 1) / ns;
   // The mapping fixes how the fused reductions are partitioned, so it must not
   // depend on the number of slots: a slot's result is then bitwise the same
@@ -351,51 +364,49 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st) {
     m.nch = (a.g.Vsh + 63) / 64;
     m.maxc = (m.nch + 7) / 8;
     m.ngroups = ngroups;
+    // tuning knob: DP_HOP_ORDER in {0, 1, 2} (block order within an XCD)
+    static const int order = std::min(2, std::max(0, env_knob("DP_HOP_ORDER", 0)));
+    m.order = order;
     nparts = 8 * a.g.T * m.maxc;
     const dim3 grid(nparts * ngroups);
     if (nt) {
       switch (ns) {
-        case 4: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 4, true>), grid, dim3(64), 0, st, a, m); break;
-        case 2: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 2, true>), grid, dim3(64), 0, st, a, m); break;
-        default: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 1, true>), grid, dim3(64), 0, st, a, m); break;
+        case 2: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 2, true, DAG>), grid, dim3(64), 0, st, a, m); break;
+        default: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 1, true, DAG>), grid, dim3(64), 0, st, a, m); break;
       }
     } else {
       switch (ns) {
-        case 4: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 4, false>), grid, dim3(64), 0, st, a, m); break;
-        case 2: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 2, false>), grid, dim3(64), 0, st, a, m); break;
-        default: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 1, false>), grid, dim3(64), 0, st, a, m); break;
+        case 2: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 2, false, DAG>), grid, dim3(64), 0, st, a, m); break;
+        default: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 1, false, DAG>), grid, dim3(64), 0, st, a, m); break;
       }
     }
   } else {
     nparts = ntiles;
     const dim3 grid(ntiles * ngroups);
     switch (ns) {
-      case 4: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 4>), grid, dim3(kBlock), 0, st, a); break;
-      case 2: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 2>), grid, dim3(kBlock), 0, st, a); break;
-      default: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 1>), grid, dim3(kBlock), 0, st, a); break;
+      case 2: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 2, DAG>), grid, dim3(kBlock), 0, st, a); break;
+      default: hipLaunchKernelGGL((hop_kernel<P, EPI, RED, 1, DAG>), grid, dim3(kBlock), 0, st, a); break;
     }
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || RED == RED_NONE) return e;
-  constexpr int nv = RED == RED_DOT_EXT ? 2 : RED == RED_TS ? 3 : 1;
-  return launch_finalize(a.red, nv, nparts, a.nslots, a.slots.mask, st);
+  *nparts_out = nparts;
+  return hipGetLastError();
 }
 
-template <int P>
-hipError_t launch_epi(const HopArgs& a, int ntiles, hipStream_t st) {
+template <int P, bool DAG>
+hipError_t launch_epi(const HopArgs& a, int ntiles, hipStream_t st, int* np) {
   // fused reductions are only used with the even-site Schur epilogue
   if (a.red.red != RED_NONE && a.epi != EPI_DIAG) return hipErrorInvalidValue;
   switch (a.epi) {
-    case EPI_HOP: return launch_ns<P, EPI_HOP, RED_NONE>(a, ntiles, st);
-    case EPI_INV: return launch_ns<P, EPI_INV, RED_NONE>(a, ntiles, st);
-    case EPI_SUB: return launch_ns<P, EPI_SUB, RED_NONE>(a, ntiles, st);
-    case EPI_INV_SUB: return launch_ns<P, EPI_INV_SUB, RED_NONE>(a, ntiles, st);
+    case EPI_HOP: return launch_ns<P, EPI_HOP, RED_NONE, DAG>(a, ntiles, st, np);
+    case EPI_INV: return launch_ns<P, EPI_INV, RED_NONE, DAG>(a, ntiles, st, np);
+    case EPI_SUB: return launch_ns<P, EPI_SUB, RED_NONE, DAG>(a, ntiles, st, np);
+    case EPI_INV_SUB: return launch_ns<P, EPI_INV_SUB, RED_NONE, DAG>(a, ntiles, st, np);
     case EPI_DIAG:
       switch (a.red.red) {
-        case RED_NONE: return launch_ns<P, EPI_DIAG, RED_NONE>(a, ntiles, st);
-        case RED_DOT_EXT: return launch_ns<P, EPI_DIAG, RED_DOT_EXT>(a, ntiles, st);
-        case RED_TS: return launch_ns<P, EPI_DIAG, RED_TS>(a, ntiles, st);
-        case RED_NORM: return launch_ns<P, EPI_DIAG, RED_NORM>(a, ntiles, st);
+        case RED_NONE: return launch_ns<P, EPI_DIAG, RED_NONE, DAG>(a, ntiles, st, np);
+        case RED_DOT_EXT: return launch_ns<P, EPI_DIAG, RED_DOT_EXT, DAG>(a, ntiles, st, np);
+        case RED_TS: return launch_ns<P, EPI_DIAG, RED_TS, DAG>(a, ntiles, st, np);
+        case RED_NORM: return launch_ns<P, EPI_DIAG, RED_NORM, DAG>(a, ntiles, st, np);
         default: return hipErrorInvalidValue;
       }
     default: return hipErrorInvalidValue;
@@ -411,14 +422,15 @@ int hop_blocks(const Geom& g) {
   return std::max(reduction_blocks(g), 8 * g.T * ((nch + 7) / 8));
 }
 
-hipError_t launch_hop(const HopArgs& a, hipStream_t st) {
+hipError_t launch_hop(const HopArgs& a, hipStream_t st, int* nparts) {
+  *nparts = 0;
   if (a.nslots <= 0 || a.g.Vh <= 0) return hipErrorInvalidValue;
   if (a.in.prec != a.out.prec || a.link_prec != a.in.prec) return hipErrorInvalidValue;
   const int ntiles = reduction_blocks(a.g);
   switch (a.in.prec) {
-    case F64: return launch_epi<F64>(a, ntiles, st);
-    case F32: return launch_epi<F32>(a, ntiles, st);
-    case F16: return launch_epi<F16>(a, ntiles, st);
+    case F64: return a.dag ? launch_epi<F64, true>(a, ntiles, st, nparts) : launch_epi<F64, false>(a, ntiles, st, nparts);
+    case F32: return a.dag ? launch_epi<F32, true>(a, ntiles, st, nparts) : launch_epi<F32, false>(a, ntiles, st, nparts);
+    case F16: return a.dag ? launch_epi<F16, true>(a, ntiles, st, nparts) : launch_epi<F16, false>(a, ntiles, st, nparts);
     default: return hipErrorInvalidValue;
   }
 }

@@ -121,7 +121,8 @@ struct dp_ctx {
   double M = 0.0;
   std::vector<double> alpha;
 
-  dp::Workspace ws_apply;           // one slot, for dp_apply
+  dp::Workspace ws_apply;           // for dp_apply / dp_apply_dev
+  std::vector<double> apply_key;    // what ws_apply's per-slot tables were built for
   dp_batch* solve_batch = nullptr;  // reused by dp_solve
   dp::DevBuf scratch_aos, bad_flag;
 
@@ -129,7 +130,9 @@ struct dp_ctx {
   struct KStat {
     long long launches = 0;
     double ms = 0.0, bytes = 0.0, flops = 0.0;
+    std::vector<float> samples;  // the first kMaxSamples launch durations
   };
+  static constexpr size_t kMaxSamples = 1 << 16;
   struct Pending {
     std::string name;
     double bytes, flops;

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -276,6 +277,7 @@ int timing_harvest(dp_ctx* c) {
     auto& k = c->kstats[q.name];
     k.launches++;
     k.ms += ms;
+    if (k.samples.size() < dp_ctx::kMaxSamples) k.samples.push_back(ms);
     k.bytes += q.bytes;
     k.flops += q.flops;
     c->ev_free.push_back(q.a);
@@ -308,13 +310,20 @@ int hop(dp_ctx* c, Workspace& w, int s0, int n, int prec, int p, int dag, int ep
   a.nslots = n;
   hipEvent_t ev = nullptr;
   DP_TRY(timing_begin(c, &ev));
-  DP_HIP(c, launch_hop(a, c->stream));
+  int nparts = 0;
+  DP_HIP(c, launch_hop(a, c->stream, &nparts));
   if (c->timing) {
     static const char* epi_names[] = {"hop", "inv", "diag", "sub", "invsub"};
     double bytes, flops;
     hop_cost(c, prec, epi, red, active_slots(c, mask, n), &bytes, &flops);
     std::string name = std::string("hop_") + prec_name(prec) + "_" + epi_names[epi] + (dag ? "_dag" : "");
     DP_TRY(timing_end(c, ev, name, bytes, flops));
+  }
+  if (red != RED_NONE) {
+    const int nv = red == RED_DOT_EXT ? 2 : red == RED_TS ? 3 : 1;
+    DP_TRY(timing_begin(c, &ev));
+    DP_HIP(c, launch_finalize(a.red, nv, nparts, n, a.slots.mask, c->stream));
+    DP_TRY(timing_end(c, ev, "finalize", 0.0, 0.0));
   }
   return DP_OK;
 }
@@ -385,6 +394,7 @@ int drop_masses(dp_ctx* c) {
   if (c->open_batches > 0) return fail(c, DP_ERR_BAD_STATE, "a batch is open on this context");
   for (auto* m : c->masses) delete m;
   c->masses.clear();
+  c->apply_key.clear();
   return DP_OK;
 }
 
@@ -571,69 +581,120 @@ int dp_set_alpha(dp_ctx* c, const double* alpha) {
   return DP_OK;
 }
 
-int dp_apply(dp_ctx* c, const double* in, double* out, int flags) {
-  if (!c || !in || !out) return fail(c, DP_ERR_INVALID_ARG, "null argument");
+}  // extern "C"
+
+namespace {
+
+int check_apply_flags(dp_ctx* c, int flags) {
   if (flags & ~(DP_PRECOND | DP_DAGGER | DP_HOP_ONLY | DP_APPLY_SCHUR | DP_APPLY_F32 | DP_APPLY_F16))
     return fail(c, DP_ERR_INVALID_ARG, "unknown flag");
   if ((flags & DP_APPLY_F32) && (flags & DP_APPLY_F16)) return fail(c, DP_ERR_INVALID_ARG, "two precisions");
   if ((flags & DP_HOP_ONLY) && (flags & DP_APPLY_SCHUR)) return fail(c, DP_ERR_INVALID_ARG, "hop-only Schur");
-  DP_HIP(c, hipSetDevice(c->device));
-  DP_TRY(check_state(c));
+  return DP_OK;
+}
+
+// The operator on n device spinors in host layout (in and out may not alias),
+// enqueued on the ctx stream.  The per-slot tables are uploaded only when the
+// mass, the alpha table, the precondition flag or the slot count changed.
+int apply_core(dp_ctx* c, const double2* in, double2* out, int n, int flags) {
   const int prec = (flags & DP_APPLY_F32) ? F32 : (flags & DP_APPLY_F16) ? F16 : F64;
   const int dag = (flags & DP_DAGGER) ? 1 : 0;
   Workspace& w = c->ws_apply;
-  DP_TRY(ensure_ws(c, w, 1, prec));
+  DP_TRY(ensure_ws(c, w, n, prec));
   MassEntry* me = nullptr;
   DP_TRY(mass_entry(c, c->M, &me));
   const Geom& g = c->g;
-  {
-    std::vector<double> ones(g.T, 1.0), rt(4 * g.T);
+  std::vector<double> key;
+  key.push_back((double)n);
+  key.push_back(c->M);
+  key.push_back((flags & DP_PRECOND) ? 1.0 : 0.0);
+  for (const void* q : {me->a64.p, me->a32.p, me->a16.p, me->s16.p, w.ratio.p}) key.push_back((double)(uintptr_t)q);
+  if (flags & DP_PRECOND) key.insert(key.end(), c->alpha.begin(), c->alpha.end());
+  if (key != c->apply_key) {
+    std::vector<double> ones(g.T, 1.0), rt(4 * g.T), all((size_t)4 * g.T * n), m4(n, 4.0 + c->M), one(n, 1.0);
     ratio_tables(g.T, c->bc_t, (flags & DP_PRECOND) ? c->alpha.data() : ones.data(), rt.data());
-    DP_TRY(h2d(c, w.ratio.p, rt.data(), sizeof(double) * 4 * g.T));
-    const double m4 = 4.0 + c->M;
-    DP_TRY(h2d(c, w.m4.p, &m4, sizeof(double)));
+    for (int k = 0; k < n; ++k) std::copy(rt.begin(), rt.end(), all.begin() + (size_t)4 * g.T * k);
+    DP_TRY(h2d(c, w.ratio.p, all.data(), sizeof(double) * all.size()));
+    DP_TRY(h2d(c, w.m4.p, m4.data(), sizeof(double) * n));
+    DP_TRY(h2d(c, w.slot_scale.p, one.data(), sizeof(double) * n));
     const void* p3[3] = {me->a64.p, me->a32.p, me->a16.p};
-    for (int k = 0; k < 3; ++k) DP_TRY(h2d(c, w.ainv_ptr[k].p, &p3[k], sizeof(void*)));
-    const float* s16 = me->s16.as<float>();
-    DP_TRY(h2d(c, w.ainv_scale_ptr.p, &s16, sizeof(float*)));
+    for (int k = 0; k < 3; ++k) {
+      std::vector<const void*> v(n, p3[k]);
+      DP_TRY(h2d(c, w.ainv_ptr[k].p, v.data(), sizeof(void*) * n));
+    }
+    std::vector<const float*> s16(n, me->s16.as<float>());
+    DP_TRY(h2d(c, w.ainv_scale_ptr.p, s16.data(), sizeof(float*) * n));
+    c->apply_key = key;
   }
-  const size_t bytes = (size_t)2 * g.Vh * 12 * sizeof(double2);
-  DP_HIP(c, c->scratch_aos.reserve(bytes));
-  DP_HIP(c, hipMemcpyAsync(c->scratch_aos.p, in, bytes, hipMemcpyHostToDevice, c->stream));
-  DP_HIP(c, launch_spinor_import(g, c->scratch_aos.as<double2>(), 1, 0, 0, w.eta_e.ref(), nullptr, c->stream));
-  DP_HIP(c, launch_spinor_import(g, c->scratch_aos.as<double2>(), 1, 0, 1, w.eta_o.ref(), nullptr, c->stream));
+  const long col = 2L * g.Vh * 12;  // double2 per column
+  DP_HIP(c, launch_spinor_import(g, in, n, col, 0, w.eta_e.ref(), nullptr, c->stream));
+  DP_HIP(c, launch_spinor_import(g, in, n, col, 1, w.eta_o.ref(), nullptr, c->stream));
   // inputs in the compute precision: even in r, odd in s (Vh sites each)
   const Field* ie = &w.eta_e;
   const Field* io = &w.eta_o;
   const Field* oe = &w.b64;
   const Field* oo = &w.to64;
   if (prec != F64) {
-    const double one = 1.0;
-    DP_TRY(h2d(c, w.slot_scale.p, &one, sizeof(double)));
-    DP_TRY(blas(c, w, 0, 1, OP_SCALE_COPY, prec, nullptr, {&w.r, &w.eta_e}));
-    DP_TRY(blas(c, w, 0, 1, OP_SCALE_COPY, prec, nullptr, {&w.s, &w.eta_o}));
+    DP_TRY(blas(c, w, 0, n, OP_SCALE_COPY, prec, nullptr, {&w.r, &w.eta_e}));
+    DP_TRY(blas(c, w, 0, n, OP_SCALE_COPY, prec, nullptr, {&w.s, &w.eta_o}));
     ie = &w.r;
     io = &w.s;
     oe = &w.v;
     oo = &w.t;
   }
   if (flags & DP_HOP_ONLY) {
-    DP_TRY(hop(c, w, 0, 1, prec, 0, dag, EPI_HOP, 0.0, *io, *oe, nullptr, nullptr));
-    DP_TRY(hop(c, w, 0, 1, prec, 1, dag, EPI_HOP, 0.0, *ie, *oo, nullptr, nullptr));
+    DP_TRY(hop(c, w, 0, n, prec, 0, dag, EPI_HOP, 0.0, *io, *oe, nullptr, nullptr));
+    DP_TRY(hop(c, w, 0, n, prec, 1, dag, EPI_HOP, 0.0, *ie, *oo, nullptr, nullptr));
   } else if (flags & DP_APPLY_SCHUR) {
-    DP_TRY(schur(c, w, 0, 1, prec, dag, *ie, w.to, *oe, nullptr, RED_NONE, FIN_NONE));
-    DP_TRY(blas(c, w, 0, 1, OP_ZERO, prec, nullptr, {oo}));
+    DP_TRY(schur(c, w, 0, n, prec, dag, *ie, w.to, *oe, nullptr, RED_NONE, FIN_NONE));
+    DP_TRY(blas(c, w, 0, n, OP_ZERO, prec, nullptr, {oo}));
   } else {
-    DP_TRY(hop(c, w, 0, 1, prec, 0, dag, EPI_DIAG, 1.0, *io, *oe, ie, nullptr));
-    DP_TRY(hop(c, w, 0, 1, prec, 1, dag, EPI_DIAG, 1.0, *ie, *oo, io, nullptr));
+    DP_TRY(hop(c, w, 0, n, prec, 0, dag, EPI_DIAG, 1.0, *io, *oe, ie, nullptr));
+    DP_TRY(hop(c, w, 0, n, prec, 1, dag, EPI_DIAG, 1.0, *ie, *oo, io, nullptr));
   }
   if (prec != F64) {
-    DP_TRY(blas(c, w, 0, 1, OP_TO64, prec, nullptr, {&w.b64, oe}));
-    DP_TRY(blas(c, w, 0, 1, OP_TO64, prec, nullptr, {&w.to64, oo}));
+    DP_TRY(blas(c, w, 0, n, OP_TO64, prec, nullptr, {&w.b64, oe}));
+    DP_TRY(blas(c, w, 0, n, OP_TO64, prec, nullptr, {&w.to64, oo}));
   }
-  DP_HIP(c, launch_spinor_export(g, w.b64.ref(), w.to64.ref(), 1, nullptr, c->scratch_aos.as<double2>(), 0,
-                                 c->stream));
-  DP_HIP(c, hipMemcpyAsync(out, c->scratch_aos.p, bytes, hipMemcpyDeviceToHost, c->stream));
+  DP_HIP(c, launch_spinor_export(g, w.b64.ref(), w.to64.ref(), n, nullptr, out, col, c->stream));
+  return DP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dp_apply(dp_ctx* c, const double* in, double* out, int flags) {
+  if (!c || !in || !out) return fail(c, DP_ERR_INVALID_ARG, "null argument");
+  DP_TRY(check_apply_flags(c, flags));
+  DP_HIP(c, hipSetDevice(c->device));
+  DP_TRY(check_state(c));
+  const Geom& g = c->g;
+  const size_t bytes = (size_t)2 * g.Vh * 12 * sizeof(double2);
+  DP_HIP(c, c->scratch_aos.reserve(2 * bytes));
+  double2* din = c->scratch_aos.as<double2>();
+  double2* dout = din + (size_t)2 * g.Vh * 12;
+  DP_HIP(c, hipMemcpyAsync(din, in, bytes, hipMemcpyHostToDevice, c->stream));
+  DP_TRY(apply_core(c, din, dout, 1, flags));
+  DP_HIP(c, hipMemcpyAsync(out, dout, bytes, hipMemcpyDeviceToHost, c->stream));
+  DP_HIP(c, hipStreamSynchronize(c->stream));
+  DP_TRY(timing_harvest(c));
+  return DP_OK;
+}
+
+int dp_apply_dev(dp_ctx* c, const void* in, void* out, int nrhs, int flags, void* stream) {
+  if (!c || !in || !out) return fail(c, DP_ERR_INVALID_ARG, "null argument");
+  if (nrhs <= 0) return fail(c, DP_ERR_INVALID_ARG, "nrhs must be positive");
+  DP_TRY(check_apply_flags(c, flags));
+  const Geom& g = c->g;
+  const size_t bytes = (size_t)nrhs * 2 * g.Vh * 12 * sizeof(double2);
+  const char* a = static_cast<const char*>(in);
+  const char* b = static_cast<const char*>(out);
+  if (a < b + bytes && b < a + bytes) return fail(c, DP_ERR_INVALID_ARG, "in and out overlap");
+  DP_HIP(c, hipSetDevice(c->device));
+  DP_TRY(check_state(c));
+  if (stream) DP_HIP(c, hipStreamSynchronize((hipStream_t)stream));
+  DP_TRY(apply_core(c, static_cast<const double2*>(in), static_cast<double2*>(out), nrhs, flags));
   DP_HIP(c, hipStreamSynchronize(c->stream));
   DP_TRY(timing_harvest(c));
   return DP_OK;
@@ -667,6 +728,18 @@ int dp_get_timing(dp_ctx* c, dp_kernel_stat* out, int max, int* count) {
     }
     ++n;
   }
+  *count = n;
+  return DP_OK;
+}
+
+int dp_get_timing_samples(dp_ctx* c, const char* name, float* ms, int max, int* count) {
+  if (!c || !name || !count || max < 0 || (max > 0 && !ms)) return fail(c, DP_ERR_INVALID_ARG, "bad argument");
+  DP_HIP(c, hipSetDevice(c->device));
+  DP_HIP(c, hipStreamSynchronize(c->stream));
+  DP_TRY(timing_harvest(c));
+  auto it = c->kstats.find(name);
+  const int n = it == c->kstats.end() ? 0 : (int)it->second.samples.size();
+  for (int k = 0; k < std::min(n, max); ++k) ms[k] = it->second.samples[k];
   *count = n;
   return DP_OK;
 }
