@@ -369,15 +369,18 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
     m.order = order;
     nparts = 8 * a.g.T * m.maxc;
     const dim3 grid(nparts * ngroups);
+    // tuning knob: DP_HOP_LDS = bytes of (unused) LDS per block, which caps the
+    // blocks resident per CU (160 KB of LDS per CU) and so the sweep front
+    static const int lds = std::min(65536, std::max(0, env_knob("DP_HOP_LDS", 0)));
     if (nt) {
       switch (ns) {
-        case 2: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 2, true, DAG>), grid, dim3(64), 0, st, a, m); break;
-        default: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 1, true, DAG>), grid, dim3(64), 0, st, a, m); break;
+        case 2: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 2, true, DAG>), grid, dim3(64), lds, st, a, m); break;
+        default: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 1, true, DAG>), grid, dim3(64), lds, st, a, m); break;
       }
     } else {
       switch (ns) {
-        case 2: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 2, false, DAG>), grid, dim3(64), 0, st, a, m); break;
-        default: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 1, false, DAG>), grid, dim3(64), 0, st, a, m); break;
+        case 2: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 2, false, DAG>), grid, dim3(64), lds, st, a, m); break;
+        default: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 1, false, DAG>), grid, dim3(64), lds, st, a, m); break;
       }
     }
   } else {
