@@ -9,7 +9,10 @@ Thin ctypes wrapper around ``oracle/liborc.so`` (built from ``orc.c`` by
 layouts ``U[T,L1,L2,L3,4,3,3]``, ``psi[T,L1,L2,L3,4,3]`` and
 ``C[T,L1,L2,L3,12,12]``.  ``alpha`` is a table of T positive numbers in the
 convention ``S' = alpha S`` (the reciprocal of the function the paper
-factorises in eq. redeft).
+factorises in eq. redeft).  ``beta`` (light-quark section, eqs. redefa and
+betaa) is a tuple of four per-direction profiles ``(alpha_0[T], alpha_1[L1],
+alpha_2[L2], alpha_3[L3])`` with ``beta(y) = prod_mu alpha_mu(y_mu)``; a
+``None`` entry is a profile of ones.
 
 The pins that make this oracle trustworthy live in ``tests/test_oracle_*.py``
 (closed-form free propagator, dense LU, similarity, gamma5-hermiticity, gauge
@@ -46,6 +49,10 @@ def _lib():
                                            ctypes.c_double, ctypes.c_double, dp, dp]
         lib.orc_solve.argtypes = [ip, ctypes.c_int, dp, dp, ctypes.c_double, dp, ctypes.c_int, dp,
                                   ctypes.c_double, ctypes.c_int, dp, dp, dp]
+        lib.orc_apply_beta.argtypes = [ip, ctypes.c_int, dp, dp, ctypes.c_double, dp, ctypes.c_int, dp, dp]
+        lib.orc_apply_modified4.argtypes = [ip, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp, dp, dp]
+        lib.orc_solve_beta.argtypes = [ip, ctypes.c_int, dp, dp, ctypes.c_double, dp, ctypes.c_int, dp,
+                                       ctypes.c_double, ctypes.c_int, dp, dp, dp]
         lib.orc_cpp.argtypes = [ip, ctypes.c_int, dp, ctypes.c_int, dp]
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         lib.orc_get_threads.restype = ctypes.c_int
@@ -123,9 +130,58 @@ def apply_modified(U, C, M, psi, alpha, alpha_T=1.0, alpha_m1=1.0, bc_t=-1):
     return out
 
 
+def _profiles(dims, beta):
+    """The four profiles of beta concatenated (T + L1 + L2 + L3 values)."""
+    assert len(beta) == 4
+    parts = [np.ones(dims[mu]) if b is None else np.asarray(b, dtype=np.float64) for mu, b in enumerate(beta)]
+    for mu, b in enumerate(parts):
+        assert b.shape == (dims[mu],)
+    return np.ascontiguousarray(np.concatenate(parts))
+
+
+def beta_field(dims, beta):
+    """beta(y) = prod_mu alpha_mu(y_mu) on the lattice, shape dims."""
+    out = np.ones(tuple(dims))
+    for mu, b in enumerate(beta):
+        if b is not None:
+            shape = [1, 1, 1, 1]
+            shape[mu] = dims[mu]
+            out = out * np.asarray(b, dtype=np.float64).reshape(shape)
+    return out
+
+
+def apply_beta(U, C, M, psi, beta, bc_t=-1, dagger=False):
+    """beta (D+M) beta^-1 psi (or its adjoint), beta(y) = prod_mu alpha_mu(y_mu)."""
+    U = _c128(U)
+    psi = _c128(psi)
+    dims = U.shape[:4]
+    out = np.zeros_like(psi)
+    prof = _profiles(dims, beta)
+    Cc = None if C is None else _c128(C)
+    _check(_lib().orc_apply_beta(_dims(dims), int(bc_t), _ptr(U), _ptr(Cc), float(M), _ptr(prof),
+                                 int(bool(dagger)), _ptr(psi), _ptr(out)), "orc_apply_beta")
+    return out
+
+
+def apply_modified4(U, C, M, psi, beta, ext, bc_t=-1):
+    """D'+M through the modified covariant derivatives in every direction, the
+    boundary rule continued with ext = [alpha_mu(L_mu), alpha_mu(-1)] per mu."""
+    U = _c128(U)
+    psi = _c128(psi)
+    dims = U.shape[:4]
+    out = np.zeros_like(psi)
+    prof = _profiles(dims, beta)
+    e = np.ascontiguousarray(ext, dtype=np.float64)
+    assert e.shape == (8,)
+    Cc = None if C is None else _c128(C)
+    _check(_lib().orc_apply_modified4(_dims(dims), int(bc_t), _ptr(U), _ptr(Cc), float(M), _ptr(prof),
+                                      _ptr(e), _ptr(psi), _ptr(out)), "orc_apply_modified4")
+    return out
+
+
 def solve(U, C, M, eta, alpha=None, r=1e-13, solver="bicgstab", maxit=100000, bc_t=-1,
-          return_prec=False, allow_unconverged=False):
-    """Solve (D+M) S = eta via the alpha-preconditioned system.
+          return_prec=False, allow_unconverged=False, beta=None):
+    """Solve (D+M) S = eta via the alpha- (or beta-) preconditioned system.
 
     Returns ``(S, info)`` (or ``(S, S', info)``) with info = dict(iters,
     relres_prec, relres).
@@ -136,11 +192,17 @@ def solve(U, C, M, eta, alpha=None, r=1e-13, solver="bicgstab", maxit=100000, bc
     S = np.zeros_like(eta)
     Sp = np.zeros_like(eta) if return_prec else None
     info = np.zeros(3)
-    a = None if alpha is None else np.ascontiguousarray(alpha, dtype=np.float64)
     Cc = None if C is None else _c128(C)
     sid = {"bicgstab": 0, "cgnr": 1}[solver]
-    rc = _lib().orc_solve(_dims(dims), int(bc_t), _ptr(U), _ptr(Cc), float(M), _ptr(a), sid,
-                          _ptr(eta), float(r), int(maxit), _ptr(S), _ptr(Sp), _ptr(info))
+    if beta is not None:
+        assert alpha is None
+        prof = _profiles(dims, beta)
+        rc = _lib().orc_solve_beta(_dims(dims), int(bc_t), _ptr(U), _ptr(Cc), float(M), _ptr(prof), sid,
+                                   _ptr(eta), float(r), int(maxit), _ptr(S), _ptr(Sp), _ptr(info))
+    else:
+        a = None if alpha is None else np.ascontiguousarray(alpha, dtype=np.float64)
+        rc = _lib().orc_solve(_dims(dims), int(bc_t), _ptr(U), _ptr(Cc), float(M), _ptr(a), sid,
+                              _ptr(eta), float(r), int(maxit), _ptr(S), _ptr(Sp), _ptr(info))
     if rc != ORC_OK and not (allow_unconverged and rc == ORC_ENOCONV):
         raise OracleError(f"orc_solve failed with code {rc} after {int(info[0])} iterations")
     d = dict(iters=int(info[0]), relres_prec=float(info[1]), relres=float(info[2]), code=rc)

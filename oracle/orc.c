@@ -28,6 +28,11 @@
  *      modified:  D + M with the time derivatives replaced by the modified
  *                 ones (the paper's modified nabla_0, nabla*_0) and the
  *                 boundary rule of eq. redeftbc for the field S'.
+ *  - the light-quark generalisation (eqs. redefa, betaa, redefcovs): the
+ *    redefinition by beta(y) = prod_mu alpha_mu(y_mu), one profile per
+ *    direction, literally beta (D+M) beta^-1, and through the modified
+ *    covariant derivatives in all four directions with the boundary rule of
+ *    eq. redeftbc applied in each direction;
  *  - the global stopping rule |(D'+M) S' - eta'| < r (eq. stopping), read as
  *    the L2 norm relative to |eta'|;
  *  - BiCGStab (van der Vorst 1992) and CG on the normal equations;
@@ -249,29 +254,35 @@ int orc_clover(const int dims[4], const double *U_, double csw, double *C_)
 /* ------------------------------------------------- the Dirac operator */
 
 /*
- * Time-direction factors of the covariant derivatives.  fwd[x0] multiplies
- * U_0(y) S(y+0) in nabla_0 at y0 = x0, bwd[x0] multiplies U_0(y-0)^+ S(y-0)
- * in nabla*_0; both include the fermion boundary sign where the step
- * crosses the time boundary.  Spatial directions carry factor 1.
+ * Factors of the covariant derivatives, per direction.  fwd[mu][x_mu]
+ * multiplies U_mu(y) S(y+mu) in nabla_mu at y_mu = x_mu, bwd[mu][x_mu]
+ * multiplies U_mu(y-mu)^+ S(y-mu) in nabla*_mu; both include the fermion
+ * boundary sign where the step crosses the boundary (time only: space is
+ * periodic).  A NULL direction carries the boundary sign only.
  */
 typedef struct {
-    const double *fwd, *bwd;
-} time_factors;
+    const double *fwd[4], *bwd[4];
+} hop_factors;
 
 /* (D + M) psi with the derivative definitions above; C may be NULL (c_sw=0).
- * tf == NULL: plain derivatives with the boundary sign only. */
+ * hf == NULL: plain derivatives with the boundary sign only. */
 static void dirac_nabla(const lattice *g, const cplx *U, const cplx *C, double M,
-                        const time_factors *tf, const cplx *in, cplx *out)
+                        const hop_factors *hf, const cplx *in, cplx *out)
 {
     const long V = g->V;
-    const int T = g->L[0];
     cplx *dpsi = malloc(sizeof(cplx) * 12 * V); /* nabla_mu psi, one mu at a time */
-    double *fwd = malloc(sizeof(double) * T), *bwd = malloc(sizeof(double) * T);
-    for (int t = 0; t < T; ++t) {
-        if (tf) { fwd[t] = tf->fwd[t]; bwd[t] = tf->bwd[t]; }
-        else {
-            fwd[t] = (t == T - 1) ? g->bc_t : 1.0;
-            bwd[t] = (t == 0) ? g->bc_t : 1.0;
+    double *fwdm[4], *bwdm[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        const int L = g->L[mu];
+        const double sign = mu == 0 ? g->bc_t : 1.0;
+        fwdm[mu] = malloc(sizeof(double) * L);
+        bwdm[mu] = malloc(sizeof(double) * L);
+        for (int t = 0; t < L; ++t) {
+            if (hf && hf->fwd[mu]) { fwdm[mu][t] = hf->fwd[mu][t]; bwdm[mu][t] = hf->bwd[mu][t]; }
+            else {
+                fwdm[mu][t] = (t == L - 1) ? sign : 1.0;
+                bwdm[mu][t] = (t == 0) ? sign : 1.0;
+            }
         }
     }
 
@@ -296,8 +307,8 @@ static void dirac_nabla(const lattice *g, const cplx *U, const cplx *C, double M
         for (long x = 0; x < V; ++x) {
             int cr, xc[4];
             long xp = step_of(g, x, mu, +1, &cr);
-            double f = 1.0;
-            if (mu == 0) { coords_of(g, x, xc); f = fwd[xc[0]]; } /* space is periodic */
+            coords_of(g, x, xc);
+            const double f = fwdm[mu][xc[mu]];
             cplx tmp[12];
             colour_mul(link(U, x, mu), 0, in + 12 * xp, tmp);
             for (int i = 0; i < 12; ++i) dpsi[12 * x + i] = f * tmp[i] - in[12 * x + i];
@@ -307,8 +318,8 @@ static void dirac_nabla(const lattice *g, const cplx *U, const cplx *C, double M
         for (long x = 0; x < V; ++x) {
             int cr, xc[4];
             long xm = step_of(g, x, mu, -1, &cr);
-            double b = 1.0;
-            if (mu == 0) { coords_of(g, x, xc); b = bwd[xc[0]]; }
+            coords_of(g, x, xc);
+            const double b = bwdm[mu][xc[mu]];
             cplx back_psi[12], back_d[12], ds[12], lap[12];
             colour_mul(link(U, xm, mu), 1, in + 12 * xm, back_psi);
             colour_mul(link(U, xm, mu), 1, dpsi + 12 * xm, back_d);
@@ -326,7 +337,8 @@ static void dirac_nabla(const lattice *g, const cplx *U, const cplx *C, double M
                 }
         }
     }
-    free(dpsi); free(fwd); free(bwd);
+    free(dpsi);
+    for (int mu = 0; mu < 4; ++mu) { free(fwdm[mu]); free(bwdm[mu]); }
 }
 
 /* gamma5 = diag(1,1,-1,-1) in this basis */
@@ -337,13 +349,25 @@ static void apply_g5(long V, const cplx *in, cplx *out)
         for (int i = 0; i < 12; ++i) out[12 * x + i] = (i < 6 ? 1.0 : -1.0) * in[12 * x + i];
 }
 
-static void scale_by_alpha(const lattice *g, const double *alpha, int inverse, const cplx *in, cplx *out)
+/* the redefinition factor at site x: beta(x) = prod_mu prof[mu][x_mu]
+ * (eq. betaa's product form; a NULL direction contributes 1, and with only
+ * prof[0] set this is the time-only alpha of eq. redeft) */
+static double beta_at(const lattice *g, const double *const prof[4], long x)
 {
-    long per_t = g->V / g->L[0];
+    int xc[4];
+    coords_of(g, x, xc);
+    double b = 1.0;
+    for (int mu = 0; mu < 4; ++mu)
+        if (prof[mu]) b *= prof[mu][xc[mu]];
+    return b;
+}
+
+static void scale_by_beta(const lattice *g, const double *const prof[4], int inverse, const cplx *in, cplx *out)
+{
 #pragma omp parallel for schedule(static)
     for (long x = 0; x < g->V; ++x) {
-        double a = alpha ? alpha[x / per_t] : 1.0;
-        double f = inverse ? 1.0 / a : a;
+        const double b = beta_at(g, prof, x);
+        const double f = inverse ? 1.0 / b : b;
         for (int i = 0; i < 12; ++i) out[12 * x + i] = f * in[12 * x + i];
     }
 }
@@ -352,33 +376,47 @@ typedef struct {
     lattice g;
     const cplx *U, *C;
     double M;
-    const double *alpha; /* NULL: no preconditioning */
+    const double *prof[4]; /* all NULL: no preconditioning */
     cplx *tmp;
 } op_ctx;
 
-/* literal preconditioned operator: D' psi = alpha (D+M) alpha^-1 psi */
+/* literal preconditioned operator: D' psi = beta (D+M) beta^-1 psi */
 static void op_prec(op_ctx *o, const cplx *in, cplx *out)
 {
-    scale_by_alpha(&o->g, o->alpha, 1, in, o->tmp);
+    scale_by_beta(&o->g, o->prof, 1, in, o->tmp);
     dirac_nabla(&o->g, o->U, o->C, o->M, NULL, o->tmp, out);
-    scale_by_alpha(&o->g, o->alpha, 0, out, out);
+    scale_by_beta(&o->g, o->prof, 0, out, out);
 }
 
-/* its adjoint: D'^+ = alpha^-1 (D+M)^+ alpha, with (D+M)^+ = gamma5 (D+M) gamma5 */
+/* its adjoint: D'^+ = beta^-1 (D+M)^+ beta, with (D+M)^+ = gamma5 (D+M) gamma5 */
 static void op_prec_dag(op_ctx *o, const cplx *in, cplx *out)
 {
-    scale_by_alpha(&o->g, o->alpha, 0, in, o->tmp);
+    scale_by_beta(&o->g, o->prof, 0, in, o->tmp);
     apply_g5(o->g.V, o->tmp, o->tmp);
     dirac_nabla(&o->g, o->U, o->C, o->M, NULL, o->tmp, out);
     apply_g5(o->g.V, out, out);
-    scale_by_alpha(&o->g, o->alpha, 1, out, out);
+    scale_by_beta(&o->g, o->prof, 1, out, out);
 }
 
-static int check_alpha(int T, const double *alpha)
+static int check_profile(int L, const double *a)
 {
-    if (!alpha) return ORC_OK;
-    for (int t = 0; t < T; ++t)
-        if (!(alpha[t] > 0) || !isfinite(alpha[t])) return ORC_EINVAL;
+    if (!a) return ORC_OK;
+    for (int t = 0; t < L; ++t)
+        if (!(a[t] > 0) || !isfinite(a[t])) return ORC_EINVAL;
+    return ORC_OK;
+}
+
+static int check_alpha(int T, const double *alpha) { return check_profile(T, alpha); }
+
+/* prof4: NULL, or T + L1 + L2 + L3 values (the four profiles one after the other) */
+static int split_profiles(const lattice *g, const double *prof4, const double *prof[4])
+{
+    long off = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        prof[mu] = prof4 ? prof4 + off : NULL;
+        if (check_profile(g->L[mu], prof[mu])) return ORC_EINVAL;
+        off += g->L[mu];
+    }
     return ORC_OK;
 }
 
@@ -389,7 +427,25 @@ int orc_apply(const int dims[4], int bc_t, const double *U, const double *C, dou
     op_ctx o;
     if (setup(&o.g, dims, bc_t) != ORC_OK || check_alpha(dims[0], alpha)) return ORC_EINVAL;
     init_gammas();
-    o.U = (const cplx *)U; o.C = (const cplx *)C; o.M = M; o.alpha = alpha;
+    o.U = (const cplx *)U; o.C = (const cplx *)C; o.M = M;
+    o.prof[0] = alpha; o.prof[1] = o.prof[2] = o.prof[3] = NULL;
+    o.tmp = malloc(sizeof(cplx) * 12 * o.g.V);
+    if (!o.tmp) return ORC_ENOMEM;
+    if (dagger) op_prec_dag(&o, (const cplx *)in, (cplx *)out);
+    else op_prec(&o, (const cplx *)in, (cplx *)out);
+    free(o.tmp);
+    return ORC_OK;
+}
+
+/* out = D' in or D'^+ in for beta(y) = prod_mu alpha_mu(y_mu) (eq. redefa);
+ * prof4 = T + L1 + L2 + L3 profile values (NULL: beta = 1) */
+int orc_apply_beta(const int dims[4], int bc_t, const double *U, const double *C, double M,
+                   const double *prof4, int dagger, const double *in, double *out)
+{
+    op_ctx o;
+    if (setup(&o.g, dims, bc_t) != ORC_OK || split_profiles(&o.g, prof4, o.prof)) return ORC_EINVAL;
+    init_gammas();
+    o.U = (const cplx *)U; o.C = (const cplx *)C; o.M = M;
     o.tmp = malloc(sizeof(cplx) * 12 * o.g.V);
     if (!o.tmp) return ORC_ENOMEM;
     if (dagger) op_prec_dag(&o, (const cplx *)in, (cplx *)out);
@@ -430,9 +486,48 @@ int orc_apply_modified(const int dims[4], int bc_t, const double *U, const doubl
             bwd[t] = alpha[t] / alpha_m1 * (bc_t * alpha_m1 / alpha[T - 1]);
         }
     }
-    time_factors tf = {fwd, bwd};
-    dirac_nabla(&g, (const cplx *)U, (const cplx *)C, M, &tf, (const cplx *)in, (cplx *)out);
+    hop_factors hf = {{fwd, NULL, NULL, NULL}, {bwd, NULL, NULL, NULL}};
+    dirac_nabla(&g, (const cplx *)U, (const cplx *)C, M, &hf, (const cplx *)in, (cplx *)out);
     free(fwd); free(bwd);
+    return ORC_OK;
+}
+
+/*
+ * D' + M for beta(y) = prod_mu alpha_mu(y_mu) through the modified covariant
+ * derivatives of eq. redefcovs in every direction (reciprocal convention as
+ * above): nabla_mu carries alpha_mu(y_mu)/alpha_mu(y_mu+1), nabla*_mu carries
+ * alpha_mu(y_mu)/alpha_mu(y_mu-1), and beyond the boundary in direction mu the
+ * field is continued as eq. redeftbc continues it in time,
+ *   S'(y + L_mu mu) = s_mu * alpha_mu(y_mu + L_mu) / alpha_mu(y_mu) * S'(y),
+ * with s_mu the fermion's boundary sign (bc_t in time, +1 in space) and the
+ * extension values ext[2 mu] = alpha_mu(L_mu), ext[2 mu + 1] = alpha_mu(-1).
+ */
+int orc_apply_modified4(const int dims[4], int bc_t, const double *U, const double *C, double M,
+                        const double *prof4, const double *ext, const double *in, double *out)
+{
+    lattice g;
+    const double *prof[4];
+    if (setup(&g, dims, bc_t) != ORC_OK || !prof4 || !ext || split_profiles(&g, prof4, prof)) return ORC_EINVAL;
+    for (int k = 0; k < 8; ++k)
+        if (!(ext[k] > 0)) return ORC_EINVAL;
+    init_gammas();
+    double *fwd[4], *bwd[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        const int L = dims[mu];
+        const double sign = mu == 0 ? bc_t : 1.0;
+        const double *a = prof[mu];
+        fwd[mu] = malloc(sizeof(double) * L);
+        bwd[mu] = malloc(sizeof(double) * L);
+        for (int t = 0; t < L; ++t) {
+            if (t + 1 < L) fwd[mu][t] = a[t] / a[t + 1];
+            else fwd[mu][t] = a[t] / ext[2 * mu] * (sign * ext[2 * mu] / a[0]);
+            if (t > 0) bwd[mu][t] = a[t] / a[t - 1];
+            else bwd[mu][t] = a[t] / ext[2 * mu + 1] * (sign * ext[2 * mu + 1] / a[L - 1]);
+        }
+    }
+    hop_factors hf = {{fwd[0], fwd[1], fwd[2], fwd[3]}, {bwd[0], bwd[1], bwd[2], bwd[3]}};
+    dirac_nabla(&g, (const cplx *)U, (const cplx *)C, M, &hf, (const cplx *)in, (cplx *)out);
+    for (int mu = 0; mu < 4; ++mu) { free(fwd[mu]); free(bwd[mu]); }
     return ORC_OK;
 }
 
@@ -551,20 +646,43 @@ static int cgnr(op_ctx *o, const cplx *b, cplx *x, double rtol, int maxit, int *
  * info[1] = true relative residual of the preconditioned system, info[2] = true
  * relative residual of the unpreconditioned system.
  */
+static int solve_prof(op_ctx *po, int solver, const double *eta, double rtol, int maxit,
+                      double *S, double *Sp, double *info);
+
 int orc_solve(const int dims[4], int bc_t, const double *U, const double *C, double M,
               const double *alpha, int solver, const double *eta, double rtol, int maxit,
               double *S, double *Sp, double *info)
 {
     op_ctx o;
     if (setup(&o.g, dims, bc_t) != ORC_OK || check_alpha(dims[0], alpha)) return ORC_EINVAL;
+    o.U = (const cplx *)U; o.C = (const cplx *)C; o.M = M;
+    o.prof[0] = alpha; o.prof[1] = o.prof[2] = o.prof[3] = NULL;
+    return solve_prof(&o, solver, eta, rtol, maxit, S, Sp, info);
+}
+
+/* the same with beta(y) = prod_mu alpha_mu(y_mu): eta' = beta eta, S = S'/beta
+ * (eqs. redefa, betaa; the restoration precedes any contraction) */
+int orc_solve_beta(const int dims[4], int bc_t, const double *U, const double *C, double M,
+                   const double *prof4, int solver, const double *eta, double rtol, int maxit,
+                   double *S, double *Sp, double *info)
+{
+    op_ctx o;
+    if (setup(&o.g, dims, bc_t) != ORC_OK || split_profiles(&o.g, prof4, o.prof)) return ORC_EINVAL;
+    o.U = (const cplx *)U; o.C = (const cplx *)C; o.M = M;
+    return solve_prof(&o, solver, eta, rtol, maxit, S, Sp, info);
+}
+
+static int solve_prof(op_ctx *po, int solver, const double *eta, double rtol, int maxit,
+                      double *S, double *Sp, double *info)
+{
+    op_ctx o = *po;
     if (solver != 0 && solver != 1) return ORC_EINVAL;
     init_gammas();
     const long n = 12 * o.g.V;
-    o.U = (const cplx *)U; o.C = (const cplx *)C; o.M = M; o.alpha = alpha;
     o.tmp = malloc(sizeof(cplx) * n);
     cplx *ep = malloc(sizeof(cplx) * n), *xp = malloc(sizeof(cplx) * n), *res = malloc(sizeof(cplx) * n);
     if (!o.tmp || !ep || !xp || !res) return ORC_ENOMEM;
-    scale_by_alpha(&o.g, alpha, 0, (const cplx *)eta, ep);
+    scale_by_beta(&o.g, o.prof, 0, (const cplx *)eta, ep);
     int iters = 0;
     int st = solver == 0 ? bicgstab(&o, ep, xp, rtol, maxit, &iters) : cgnr(&o, ep, xp, rtol, maxit, &iters);
     /* true residuals */
@@ -574,9 +692,9 @@ int orc_solve(const int dims[4], int bc_t, const double *U, const double *C, dou
     for (long i = 0; i < n; ++i) res[i] = ep[i] - res[i];
     rn = sqrt(norm2(n, res));
     if (Sp) memcpy(Sp, xp, n * sizeof(cplx));
-    scale_by_alpha(&o.g, alpha, 1, xp, (cplx *)S);
+    scale_by_beta(&o.g, o.prof, 1, xp, (cplx *)S);
     op_ctx plain = o;
-    plain.alpha = NULL;
+    plain.prof[0] = plain.prof[1] = plain.prof[2] = plain.prof[3] = NULL;
     op_prec(&plain, (const cplx *)S, res);
     const cplx *e = (const cplx *)eta;
 #pragma omp parallel for schedule(static)

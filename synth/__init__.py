@@ -32,5 +32,5 @@ from .fields import (  # noqa: F401
     gauge_transform,
     volume,
 )
-from .profiles import alpha_exp, alpha_exp_sym, alpha_cosh_paper, alpha_table  # noqa: F401
+from .profiles import alpha_exp, alpha_exp_sym, alpha_cosh_paper, alpha_table, beta_cosh_paper  # noqa: F401
 from .configs import CONFIGS, config  # noqa: F401

@@ -34,6 +34,13 @@ def alpha_cosh_paper(T, alpha0, x0_src=0):
     return 1.0 / np.cosh(alpha0 * (t - T / 2.0))
 
 
+def beta_cosh_paper(dims, alpha0):
+    """The light-quark factorisation beta(y) = prod_mu 1/cosh[alpha0 (y_mu - L_mu/2)]
+    (eq. betaa), returned in this module's convention (S' = beta S) as its four
+    per-direction profiles: cosh[alpha0 (y_mu - L_mu/2)] for mu = 0..3."""
+    return tuple(np.cosh(alpha0 * (np.arange(L, dtype=np.float64) - L / 2.0)) for L in dims)
+
+
 def alpha_table(kind, T, alpha0, x0_src=0):
     kinds = {"exp": alpha_exp, "exp_sym": alpha_exp_sym, "cosh": alpha_cosh_paper}
     if kind not in kinds:
