@@ -131,6 +131,17 @@ int dp_set_kappa(dp_ctx* ctx, double kappa);
 /* Distance profile alpha(x0), T entries, each finite and > 0. */
 int dp_set_alpha(dp_ctx* ctx, const double* alpha);
 
+/* Spatial profiles of the light-quark factorisation (light-quark section,
+ * eqs. redefa, betaa, redefcovs): S' = beta S, eta' = beta eta with
+ * beta(y) = alpha(y0) a1(y1) a2(y2) a3(y3), alpha the time profile (the
+ * ctx's, or a batch slot's own).  a1, a2, a3 hold L1, L2, L3 entries, each
+ * finite and > 0; NULL means ones (all NULL: time-only, the default).  The
+ * spatial hops then carry a_k(y_k)/a_k(y_k +- 1) (space stays periodic), and
+ * the restoration S = S'/beta precedes the contraction of C_PP.  Applies to
+ * every later solve, batch admission and dp_apply with DP_PRECOND on this ctx;
+ * DP_ERR_BAD_STATE while a batch is open. */
+int dp_set_alpha_space(dp_ctx* ctx, const double* a1, const double* a2, const double* a3);
+
 /* out = op(in) for one full-lattice spinor (host layout).  flags:
  * DP_PRECOND (alpha-preconditioned operator), DP_DAGGER (adjoint),
  * DP_HOP_ONLY (hopping term only) or DP_APPLY_SCHUR (even-odd Schur

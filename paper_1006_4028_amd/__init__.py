@@ -94,6 +94,23 @@ class Lattice:
         assert a.shape == (self.T,)
         self._check(self._L.dp_set_alpha(self._h, _ptr(a)))
 
+    def set_alpha_space(self, a1=None, a2=None, a3=None):
+        """Spatial profiles of the light-quark factorisation (None: ones)."""
+        arrs = []
+        for a, L in ((a1, self.dims[1]), (a2, self.dims[2]), (a3, self.dims[3])):
+            if a is None:
+                arrs.append(None)
+            else:
+                a = np.ascontiguousarray(a, dtype=np.float64)
+                assert a.shape == (L,)
+                arrs.append(a)
+        self._check(self._L.dp_set_alpha_space(self._h, *[_ptr(a) if a is not None else None for a in arrs]))
+
+    def set_beta(self, beta):
+        """beta(y) = prod_mu a_mu(y_mu) from four profiles (None: ones)."""
+        self.set_alpha(np.ones(self.T) if beta[0] is None else beta[0])
+        self.set_alpha_space(*beta[1:])
+
     # ------------------------------------------------------------ operator
     def apply(self, psi, precond=False, dagger=False, hop_only=False, schur=False, precision="f64"):
         psi = _c128(psi)

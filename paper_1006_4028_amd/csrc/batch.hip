@@ -205,10 +205,11 @@ int finish(dp_batch* b, const std::vector<int>& fin) {
     dp_batch::Slot& h = b->slots[s];
     h.hops += 1;
     DP_HIP(c, launch_cpp(g, w.x64.ref(s), w.to64.ref(s), 1, w.alpha.as<double>() + (size_t)s * g.T,
-                         w.x0src.as<int>() + s, w.cpp.as<double>() + (size_t)s * g.T, c->stream));
+                         space_profile(c), w.x0src.as<int>() + s, w.cpp.as<double>() + (size_t)s * g.T,
+                         c->stream));
     if (h.S_dev)
       DP_HIP(c, launch_spinor_export(g, w.x64.ref(s), w.to64.ref(s), 1, w.alpha.as<double>() + (size_t)s * g.T,
-                                     static_cast<double2*>(h.S_dev), 0, c->stream));
+                                     space_profile(c), static_cast<double2*>(h.S_dev), 0, c->stream));
   }
   std::vector<double> all((size_t)n * g.T);
   DP_HIP(c, hipMemcpyAsync(all.data(), w.cpp.p, sizeof(double) * g.T * n, hipMemcpyDeviceToHost, c->stream));
@@ -315,8 +316,8 @@ int dp_batch_admit(dp_batch* b, int ncols, const void* eta_dev, void* S_dev, dou
     DP_TRY(upload_slot(b, s));
     const double2* src = static_cast<const double2*>(eta_dev) + (size_t)j * col;
     const double* am = w.alpha.as<double>() + (size_t)s * g.T;
-    DP_HIP(c, launch_spinor_import(g, src, 1, 0, 0, w.eta_e.ref(s), am, c->stream));
-    DP_HIP(c, launch_spinor_import(g, src, 1, 0, 1, w.eta_o.ref(s), am, c->stream));
+    DP_HIP(c, launch_spinor_import(g, src, 1, 0, 0, w.eta_e.ref(s), am, space_profile(c), c->stream));
+    DP_HIP(c, launch_spinor_import(g, src, 1, 0, 1, w.eta_o.ref(s), am, space_profile(c), c->stream));
     pend[s] = 1;
     if (slots_out) slots_out[j] = s;
   }

@@ -139,6 +139,11 @@ struct HopArgs {
   SlotTable slots;
   ReduceRef red;
   int nslots;
+  // spatial hop ratios of the light-quark factorisation (all ones without it):
+  // direction k = 1, 2, 3 at offset 4 (L1 + .. + L_{k-1}), four tables of L_k
+  // entries each: fwd[x_k] = a_k(x_k)/a_k(x_k+1), bwd[x_k] = a_k(x_k)/a_k(x_k-1)
+  // (periodic), then the same for 1/a_k (the adjoint)
+  const double* sratio;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -173,15 +178,18 @@ hipError_t launch_clover_convert(const Geom& g, const double2* C64, void* out, f
 
 // Host-layout spinors [slot][site][4][3] complex128 (device) <-> parity fields.
 // alpha_mul: optional [nslots][T] factors applied on the way (nullptr = 1).
+// alpha_mul / alpha_div: per-slot time profiles [slot][T] (nullable); sprof:
+// the spatial profiles a_1[L1], a_2[L2], a_3[L3] one after the other (nullable)
 hipError_t launch_spinor_import(const Geom& g, const double2* aos, int nslots, long aos_slot_stride,
-                                int p, SpinorRef dst, const double* alpha_mul, hipStream_t stream);
+                                int p, SpinorRef dst, const double* alpha_mul, const double* sprof,
+                                hipStream_t stream);
 hipError_t launch_spinor_export(const Geom& g, SpinorRef even, SpinorRef odd, int nslots,
-                                const double* alpha_div, double2* aos, long aos_slot_stride,
+                                const double* alpha_div, const double* sprof, double2* aos, long aos_slot_stride,
                                 hipStream_t stream);
 // Per-timeslice sum of |psi|^2 over both parities, written to cpp[slot][t]
 // (as -sum, t = (x0 - x0_src[slot]) mod T), FP64 fields, divided by alpha^2.
 hipError_t launch_cpp(const Geom& g, SpinorRef even, SpinorRef odd, int nslots, const double* alpha,
-                      const int* x0_src, double* cpp, hipStream_t stream);
+                      const double* sprof, const int* x0_src, double* cpp, hipStream_t stream);
 
 // ------------------------------------------------------------- BLAS kernels
 // Vector kernels over the even sites of every active slot.  Krylov vectors

@@ -6,10 +6,12 @@
 //   H psi(x) = -1/2 sum_mu [ c+_mu(x) (1 - gamma_mu) U_mu(x) psi(x+mu)
 //                          + c-_mu(x) (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu) ]
 //
-// where the spatial c = 1 and the time factors are the ratios of the modified
-// time derivatives (heavy-quark section): c+_0(x) = alpha(x0)/alpha(x0+1) and
-// c-_0(x) = alpha(x0)/alpha(x0-1), with the fermion boundary sign folded in at
-// the wrap-around (the boundary rule eq. redeftbc reduces to exactly this).
+// where the time factors are the ratios of the modified time derivatives
+// (heavy-quark section): c+_0(x) = alpha(x0)/alpha(x0+1) and c-_0(x) =
+// alpha(x0)/alpha(x0-1), per slot, with the fermion boundary sign folded in at
+// the wrap-around (the boundary rule eq. redeftbc reduces to exactly this),
+// and the spatial factors are 1, or the same ratios of the spatial profiles
+// of the light-quark factorisation (eqs. betaa, redefcovs; periodic).
 // The adjoint hop (dag = 1) swaps the projectors and uses the reciprocal
 // ratios; it is the hopping part of gamma5 D'(1/alpha) gamma5 = D'(alpha)^+.
 //
@@ -122,6 +124,13 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
   constexpr int S = DAG ? -1 : 1;
   const Geom& g = a.g;
   const int L = MU == 0 ? g.T : MU == 1 ? g.L1 : MU == 2 ? g.L2 : g.L3;
+  // spatial ratios of the light-quark factorisation (the time ones are per slot)
+  R sf = R(1), sb = R(1);
+  if constexpr (MU != 0) {
+    const double* t = a.sratio + (MU == 1 ? 0 : MU == 2 ? 4 * g.L1 : 4 * (g.L1 + g.L2));
+    sf = (R)t[(DAG ? 2 * L : 0) + x[MU]];
+    sb = (R)t[(DAG ? 3 * L : L) + x[MU]];
+  }
   int y[4] = {x[0], x[1], x[2], x[3]};
   cx<R> psi[12], u[9];
   Half<R> h, w;
@@ -135,7 +144,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
       const R sc = SpinorIO<P>::load_unscaled(a.in, sl[k], jf, g.Vh, psi);
       project<MU, S>(psi, h);
       link_mul(u, h, w);
-      accumulate<MU, S>(acc[k], w, MU == 0 ? cf[k] * sc : sc);
+      accumulate<MU, S>(acc[k], w, (MU == 0 ? cf[k] : sf) * sc);
     }
   }
   // backward neighbour x - mu
@@ -148,7 +157,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
       const R sc = SpinorIO<P>::load_unscaled(a.in, sl[k], jb, g.Vh, psi);
       project<MU, -S>(psi, h);
       link_dag_mul(u, h, w);
-      accumulate<MU, -S>(acc[k], w, MU == 0 ? cb[k] * sc : sc);
+      accumulate<MU, -S>(acc[k], w, (MU == 0 ? cb[k] : sb) * sc);
     }
   }
 }

@@ -1,13 +1,21 @@
 // Layout kernels: host-order (x0 slowest, complex128 interleaved) fields to the
 // structure-of-arrays parity layout and back, precision conversion, the source
-// redefinition eta' = alpha eta, the restoration S = S'/alpha and the per-
+// redefinition eta' = beta eta, the restoration S = S'/beta and the per-
 // timeslice correlator C_PP(y0) = -sum_y tr[S^+ S] (heavy-quark section,
-// restoration eq. backcorrection in the form C = C'/alpha^2).
+// restoration eq. backcorrection in the form C = C'/alpha^2).  beta(y) =
+// alpha(y0) a_1(y1) a_2(y2) a_3(y3): the time profile alpha of eq. redeft and
+// the spatial factors of the light-quark factorisation (eqs. redefa, betaa),
+// which must be divided out site by site before the contraction.
 #include "dp_device.h"
 
 namespace dp {
 
 namespace {
+
+// a_1(x1) a_2(x2) a_3(x3), or 1 without spatial profiles
+__device__ __forceinline__ double space_factor(const Geom& g, const double* sprof, int x1, int x2, int x3) {
+  return sprof ? sprof[x1] * sprof[g.L1 + x2] * sprof[g.L1 + g.L2 + x3] : 1.0;
+}
 
 __device__ __forceinline__ void lex_coords(const Geom& g, long s, int& x0, int& x1, int& x2, int& x3) {
   x3 = (int)(s % g.L3);
@@ -42,16 +50,16 @@ __global__ void gauge_reorder_kernel(Geom g, const double2* __restrict__ U, void
     }
 }
 
-// host-order spinors -> FP64 parity field, optionally times alpha(x0)
+// host-order spinors -> FP64 parity field, optionally times beta(x)
 __global__ void spinor_import_kernel(Geom g, const double2* __restrict__ aos, long aos_ss, int p, SpinorRef dst,
-                                     const double* __restrict__ amul) {
+                                     const double* __restrict__ amul, const double* __restrict__ sprof) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int slot = blockIdx.y;
   if (i >= g.Vh) return;
   int x0, x1, x2, x3;
   eo_coords(g, p, i, x0, x1, x2, x3);
   const long s = ((long)(x0 * g.L1 + x1) * g.L2 + x2) * g.L3 + x3;
-  const double f = amul ? amul[(long)slot * g.T + x0] : 1.0;
+  const double f = (amul ? amul[(long)slot * g.T + x0] : 1.0) * space_factor(g, sprof, x1, x2, x3);
   const double2* src = aos + slot * aos_ss + s * 12;
   double2* d = static_cast<double2*>(dst.data) + slot * dst.slot_stride;
   for (int c = 0; c < 12; ++c) {
@@ -60,9 +68,9 @@ __global__ void spinor_import_kernel(Geom g, const double2* __restrict__ aos, lo
   }
 }
 
-// FP64 parity fields -> host-order spinors, optionally divided by alpha(x0)
+// FP64 parity fields -> host-order spinors, optionally divided by beta(x)
 __global__ void spinor_export_kernel(Geom g, SpinorRef e, SpinorRef o, const double* __restrict__ adiv,
-                                     double2* __restrict__ aos, long aos_ss) {
+                                     const double* __restrict__ sprof, double2* __restrict__ aos, long aos_ss) {
   const long V = 2L * g.Vh;
   const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int slot = blockIdx.y;
@@ -73,7 +81,7 @@ __global__ void spinor_export_kernel(Geom g, SpinorRef e, SpinorRef o, const dou
   const int i = (int)(s >> 1);
   const SpinorRef& f = p ? o : e;
   const double2* src = static_cast<const double2*>(f.data) + slot * f.slot_stride;
-  const double inv = adiv ? 1.0 / adiv[(long)slot * g.T + x0] : 1.0;
+  const double inv = 1.0 / ((adiv ? adiv[(long)slot * g.T + x0] : 1.0) * space_factor(g, sprof, x1, x2, x3));
   double2* d = aos + slot * aos_ss + s * 12;
   for (int c = 0; c < 12; ++c) {
     const double2 v = src[(long)c * g.Vh + i];
@@ -81,10 +89,11 @@ __global__ void spinor_export_kernel(Geom g, SpinorRef e, SpinorRef o, const dou
   }
 }
 
-// One block per (timeslice, slot): -sum over both parities of |psi|^2 / alpha^2.
+// One block per (timeslice, slot): -sum over both parities of |psi|^2 / beta^2
+// (the time factor alpha^2 after the sum, the spatial ones per site).
 __global__ void __launch_bounds__(kBlock) cpp_kernel(Geom g, SpinorRef e, SpinorRef o,
-                                                     const double* __restrict__ alpha, const int* __restrict__ x0src,
-                                                     double* __restrict__ cpp) {
+                                                     const double* __restrict__ alpha, const double* __restrict__ sprof,
+                                                     const int* __restrict__ x0src, double* __restrict__ cpp) {
   const int x0 = blockIdx.x, slot = blockIdx.y;
   __shared__ double lds[kBlock / 64];
   double acc = 0.0;
@@ -93,10 +102,18 @@ __global__ void __launch_bounds__(kBlock) cpp_kernel(Geom g, SpinorRef e, Spinor
     const double2* src = static_cast<const double2*>(f.data) + slot * f.slot_stride;
     for (int k = threadIdx.x; k < g.Vsh; k += kBlock) {
       const int i = x0 * g.Vsh + k;
+      double site = 0.0;
       for (int c = 0; c < 12; ++c) {
         const double2 v = src[(long)c * g.Vh + i];
-        acc += v.x * v.x + v.y * v.y;
+        site += v.x * v.x + v.y * v.y;
       }
+      if (sprof) {
+        int y0, y1, y2, y3;
+        eo_coords(g, par, i, y0, y1, y2, y3);
+        const double f = space_factor(g, sprof, y1, y2, y3);
+        site /= f * f;
+      }
+      acc += site;
     }
   }
   acc = wave_sum(acc);
@@ -126,26 +143,26 @@ hipError_t launch_gauge_reorder(const Geom& g, const double2* U_aos, void* U_eo[
 }
 
 hipError_t launch_spinor_import(const Geom& g, const double2* aos, int nslots, long aos_ss, int p, SpinorRef dst,
-                                const double* alpha_mul, hipStream_t st) {
+                                const double* alpha_mul, const double* sprof, hipStream_t st) {
   if (dst.prec != F64 || nslots <= 0) return hipErrorInvalidValue;
   const dim3 grid((g.Vh + kBlock - 1) / kBlock, nslots);
-  hipLaunchKernelGGL(spinor_import_kernel, grid, dim3(kBlock), 0, st, g, aos, aos_ss, p, dst, alpha_mul);
+  hipLaunchKernelGGL(spinor_import_kernel, grid, dim3(kBlock), 0, st, g, aos, aos_ss, p, dst, alpha_mul, sprof);
   return hipGetLastError();
 }
 
 hipError_t launch_spinor_export(const Geom& g, SpinorRef even, SpinorRef odd, int nslots, const double* alpha_div,
-                                double2* aos, long aos_ss, hipStream_t st) {
+                                const double* sprof, double2* aos, long aos_ss, hipStream_t st) {
   if (even.prec != F64 || odd.prec != F64 || nslots <= 0) return hipErrorInvalidValue;
   const long V = 2L * g.Vh;
   const dim3 grid((unsigned)((V + kBlock - 1) / kBlock), nslots);
-  hipLaunchKernelGGL(spinor_export_kernel, grid, dim3(kBlock), 0, st, g, even, odd, alpha_div, aos, aos_ss);
+  hipLaunchKernelGGL(spinor_export_kernel, grid, dim3(kBlock), 0, st, g, even, odd, alpha_div, sprof, aos, aos_ss);
   return hipGetLastError();
 }
 
-hipError_t launch_cpp(const Geom& g, SpinorRef even, SpinorRef odd, int nslots, const double* alpha, const int* x0src,
-                      double* cpp, hipStream_t st) {
+hipError_t launch_cpp(const Geom& g, SpinorRef even, SpinorRef odd, int nslots, const double* alpha,
+                      const double* sprof, const int* x0src, double* cpp, hipStream_t st) {
   if (even.prec != F64 || odd.prec != F64 || nslots <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(cpp_kernel, dim3(g.T, nslots), dim3(kBlock), 0, st, g, even, odd, alpha, x0src, cpp);
+  hipLaunchKernelGGL(cpp_kernel, dim3(g.T, nslots), dim3(kBlock), 0, st, g, even, odd, alpha, sprof, x0src, cpp);
   return hipGetLastError();
 }
 

@@ -86,6 +86,7 @@ struct MassEntry {
 // Device work space of a set of slots at one inner precision.
 struct Workspace {
   int nslots = 0, prec = -1;
+  const double* sratio = nullptr;  // the ctx's spatial hop ratios these slots use
   // FP64: redefined source (both parities), Schur right-hand side, solution,
   // FP64 residual, Schur result, odd temporary / odd solution
   Field eta_e, eta_o, b64, x64, r64, t64, to64;
@@ -120,6 +121,11 @@ struct dp_ctx {
 
   double M = 0.0;
   std::vector<double> alpha;
+  // spatial profiles a_1, a_2, a_3 of the light-quark factorisation: two
+  // variants on the device (0: ones, 1: the current ones), each 4 S ratios
+  // (HopArgs::sratio layout) followed by the S profile values, S = L1+L2+L3
+  dp::DevBuf space;
+  bool has_space = false;
 
   dp::Workspace ws_apply;           // for dp_apply / dp_apply_dev
   std::vector<double> apply_key;    // what ws_apply's per-slot tables were built for
@@ -201,6 +207,10 @@ int ensure_ws(dp_ctx* c, Workspace& w, int nslots, int prec);
 int h2d(dp_ctx* c, void* dst, const void* src, size_t bytes);
 int upload_mask(dp_ctx* c, Workspace& w, DevBuf& dst, const std::vector<int>& m, int staging);
 int timing_harvest(dp_ctx* c);
+// spatial tables of the light-quark factorisation (see dp_ctx::space)
+int upload_space(dp_ctx* c, const double* const a[3]);
+const double* space_ratios(dp_ctx* c, int variant);
+const double* space_profile(dp_ctx* c);  // nullptr without spatial profiles
 SlotTable slot_table(Workspace& w, int T, int s0, int prec, const int* mask);
 
 // launch helpers over slots [s0, s0 + n) of a workspace

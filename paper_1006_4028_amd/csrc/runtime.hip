@@ -83,6 +83,48 @@ void ratio_tables(int T, int bc_t, const double* alpha, double* out) {
   }
 }
 
+// The spatial tables of the light-quark factorisation for profiles a[0..2]
+// (NULL: ones): variant 0 is all ones, variant 1 the given profiles; each is
+// 4 S ratios (fwd, bwd, fwd_dag, bwd_dag per direction, periodic) followed by
+// the S profile values, S = L1 + L2 + L3.
+int upload_space(dp_ctx* c, const double* const a[3]) {
+  const Geom& g = c->g;
+  const int Ls[3] = {g.L1, g.L2, g.L3};
+  const int S = g.L1 + g.L2 + g.L3;
+  std::vector<double> h((size_t)10 * S, 1.0);
+  double* r = h.data() + 5 * S;  // variant 1
+  int off = 0, poff = 4 * S;
+  for (int k = 0; k < 3; ++k) {
+    const int L = Ls[k];
+    for (int x = 0; x < L; ++x) {
+      const double v = a[k] ? a[k][x] : 1.0;
+      const double vp = a[k] ? a[k][(x + 1) % L] : 1.0;
+      const double vm = a[k] ? a[k][(x - 1 + L) % L] : 1.0;
+      r[off + x] = v / vp;
+      r[off + L + x] = v / vm;
+      r[off + 2 * L + x] = vp / v;
+      r[off + 3 * L + x] = vm / v;
+      r[poff + x] = v;
+    }
+    off += 4 * L;
+    poff += L;
+  }
+  DP_HIP(c, c->space.reserve(sizeof(double) * h.size()));
+  DP_TRY(h2d(c, c->space.p, h.data(), sizeof(double) * h.size()));
+  c->has_space = a[0] || a[1] || a[2];
+  return DP_OK;
+}
+
+const double* space_ratios(dp_ctx* c, int variant) {
+  const Geom& g = c->g;
+  return c->space.as<double>() + (size_t)variant * 5 * (g.L1 + g.L2 + g.L3);
+}
+
+const double* space_profile(dp_ctx* c) {
+  const Geom& g = c->g;
+  return c->has_space ? space_ratios(c, 1) + 4 * (g.L1 + g.L2 + g.L3) : nullptr;
+}
+
 // Per-mass A_oo^-1 in every precision (cached per (field, clover, M)).
 int mass_entry(dp_ctx* c, double M, MassEntry** out) {
   for (auto* m : c->masses)
@@ -305,6 +347,7 @@ int hop(dp_ctx* c, Workspace& w, int s0, int n, int prec, int p, int dag, int ep
   a.clov.data = prec == F64 ? c->C64[p].p : prec == F32 ? c->C32[p].p : c->C16[p].p;
   a.clov.scale = prec == F16 ? c->C16s[p].as<float>() : nullptr;
   a.slots = slot_table(w, c->g.T, s0, prec, mask);
+  a.sratio = w.sratio ? w.sratio : space_ratios(c, 1);
   a.red = reduce_ref(w, s0, red, fin, inner_mask);
   if (wv) a.red.w = wv->ref(s0);
   a.nslots = n;
@@ -474,7 +517,9 @@ int dp_create(const int dims[4], int bc_t, int device, dp_ctx** out) {
     return DP_ERR_DEVICE;
   }
   c->alpha.assign(g.T, 1.0);
-  int rc = set_gauge_common(c, nullptr, c->stream);  // unit links, no clover
+  const double* none[3] = {nullptr, nullptr, nullptr};
+  int rc = upload_space(c, none);
+  if (rc == DP_OK) rc = set_gauge_common(c, nullptr, c->stream);  // unit links, no clover
   if (rc != DP_OK) {
     delete c;
     return rc;
@@ -581,6 +626,24 @@ int dp_set_alpha(dp_ctx* c, const double* alpha) {
   return DP_OK;
 }
 
+int dp_set_alpha_space(dp_ctx* c, const double* a1, const double* a2, const double* a3) {
+  if (!c) return DP_ERR_INVALID_ARG;
+  const double* a[3] = {a1, a2, a3};
+  const int Ls[3] = {c->g.L1, c->g.L2, c->g.L3};
+  for (int k = 0; k < 3; ++k)
+    if (a[k])
+      for (int x = 0; x < Ls[k]; ++x)
+        if (!(a[k][x] > 0) || !std::isfinite(a[k][x]) || !std::isfinite(1.0 / a[k][x]))
+          return fail(c, DP_ERR_INVALID_ARG, "spatial profiles must be finite and positive");
+  DP_HIP(c, hipSetDevice(c->device));
+  if (c->solve_batch) {  // the batch dp_solve keeps between calls
+    dp_batch_close(c->solve_batch);
+    c->solve_batch = nullptr;
+  }
+  if (c->open_batches > 0) return fail(c, DP_ERR_BAD_STATE, "a batch is open on this context");
+  return upload_space(c, a);
+}
+
 }  // extern "C"
 
 namespace {
@@ -601,6 +664,7 @@ int apply_core(dp_ctx* c, const double2* in, double2* out, int n, int flags) {
   const int dag = (flags & DP_DAGGER) ? 1 : 0;
   Workspace& w = c->ws_apply;
   DP_TRY(ensure_ws(c, w, n, prec));
+  w.sratio = space_ratios(c, (flags & DP_PRECOND) ? 1 : 0);
   MassEntry* me = nullptr;
   DP_TRY(mass_entry(c, c->M, &me));
   const Geom& g = c->g;
@@ -627,8 +691,8 @@ int apply_core(dp_ctx* c, const double2* in, double2* out, int n, int flags) {
     c->apply_key = key;
   }
   const long col = 2L * g.Vh * 12;  // double2 per column
-  DP_HIP(c, launch_spinor_import(g, in, n, col, 0, w.eta_e.ref(), nullptr, c->stream));
-  DP_HIP(c, launch_spinor_import(g, in, n, col, 1, w.eta_o.ref(), nullptr, c->stream));
+  DP_HIP(c, launch_spinor_import(g, in, n, col, 0, w.eta_e.ref(), nullptr, nullptr, c->stream));
+  DP_HIP(c, launch_spinor_import(g, in, n, col, 1, w.eta_o.ref(), nullptr, nullptr, c->stream));
   // inputs in the compute precision: even in r, odd in s (Vh sites each)
   const Field* ie = &w.eta_e;
   const Field* io = &w.eta_o;
@@ -656,7 +720,7 @@ int apply_core(dp_ctx* c, const double2* in, double2* out, int n, int flags) {
     DP_TRY(blas(c, w, 0, n, OP_TO64, prec, nullptr, {&w.b64, oe}));
     DP_TRY(blas(c, w, 0, n, OP_TO64, prec, nullptr, {&w.to64, oo}));
   }
-  DP_HIP(c, launch_spinor_export(g, w.b64.ref(), w.to64.ref(), n, nullptr, out, col, c->stream));
+  DP_HIP(c, launch_spinor_export(g, w.b64.ref(), w.to64.ref(), n, nullptr, nullptr, out, col, c->stream));
   return DP_OK;
 }
 

@@ -28,8 +28,12 @@ def parity_mask(dims):
 
 def oracle_hop(oracle, U, C, M, psi, alpha, bc_t=-1, dagger=False):
     """The hopping part of D' (or of D'^+) from the oracle: D'psi - (4 + M + C) psi
-    (the clover term is Hermitian, so it is the same diagonal for the adjoint)."""
-    full = oracle.apply(U, C, M, psi, alpha=alpha, bc_t=bc_t, dagger=dagger)
+    (the clover term is Hermitian, so it is the same diagonal for the adjoint).
+    alpha: a time profile, or a tuple of four per-direction profiles (beta)."""
+    if isinstance(alpha, tuple):
+        full = oracle.apply_beta(U, C, M, psi, alpha, bc_t=bc_t, dagger=dagger)
+    else:
+        full = oracle.apply(U, C, M, psi, alpha=alpha, bc_t=bc_t, dagger=dagger)
     diag = (4.0 + M) * psi
     if C is not None:
         diag = diag + np.einsum("...ij,...j->...i", C, psi.reshape(psi.shape[:4] + (12,))).reshape(psi.shape)

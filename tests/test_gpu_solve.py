@@ -200,3 +200,41 @@ def test_fp16_point_source_long_support(solver):
     assert info[0]["status"] == 0
     assert np.isfinite(S).all()
     assert true_residual(U, C, M, alpha, S[0], eta[0]) <= 1.0001 * r
+
+
+@pytest.mark.parametrize("solver,precision", [("bicgstab", "f64"), ("bicgstab", "f32"), ("cgnr", "f16")])
+def test_light_quark_factorisation_solve_vs_oracle(solver, precision):
+    """Solves with beta(y) = prod_mu cosh[alpha0 (y_mu - L_mu/2)] (the paper's
+    eq. betaa in the convention S' = beta S): the restored S and C_PP (the
+    restoration precedes the contraction, light-quark section) equal the
+    oracle's, and the oracle recomputes the residual of the preconditioned
+    system from the returned S.  Changing the spatial profiles while a batch
+    is open is refused."""
+    dims, M, r = (8, 4, 6, 4), 0.1, 1e-10
+    log(f"test_light_quark_factorisation_solve_vs_oracle {solver} {precision}")
+    U = synth.gauge_su3(dims, 0.3, 77)
+    C = oracle.clover(U, 1.6)
+    beta = synth.beta_cosh_paper(dims, 0.3)
+    eta = synth.point_sources_12(dims, (0, 0, 0, 0), ncols=2)
+    with lattice(dims) as L:
+        L.set_gauge(U)
+        L.set_clover(1.6)
+        L.set_mass(M)
+        L.set_beta(beta)
+        S, cpp, info = L.solve(eta, r=r, solver=solver, precision=precision, max_iter=50000)
+        import paper_1006_4028_amd as dp
+        b = dp.Batch(L, 2, "f32")
+        with pytest.raises(dp.DPError) as e:
+            L.set_alpha_space(None, None, None)
+        assert e.value.code == -7
+        b.close()
+        L.set_alpha_space(None, None, None)
+    bf = oracle.beta_field(dims, beta)[..., None, None]
+    log("  iters", [i["iters"] for i in info])
+    for k in range(2):
+        assert info[k]["status"] == 0
+        S_or, _ = oracle.solve(U, C, M, eta[k], beta=beta, r=1e-13)
+        res = bf * eta[k] - oracle.apply_beta(U, C, M, bf * S[k], beta)
+        assert np.linalg.norm(res) / np.linalg.norm(bf * eta[k]) <= 1.0001 * r
+        np.testing.assert_allclose(cpp[k], oracle.cpp(S[k]), rtol=1e-12)
+        assert np.abs(cpp[k] / oracle.cpp(S_or) - 1).max() < 1e-7
