@@ -246,6 +246,7 @@ int dp_batch_open(dp_ctx* c, int nslots, int precision, int solver, dp_batch** o
   b->prec = precision;
   b->solver = solver;
   int rc = ensure_ws(c, b->w, nslots, precision);
+  b->w.sratio = space_hop_ratios(c);  // fixed while the batch is open
   if (rc != DP_OK) {
     delete b;
     return rc;

@@ -139,7 +139,7 @@ struct HopArgs {
   SlotTable slots;
   ReduceRef red;
   int nslots;
-  // spatial hop ratios of the light-quark factorisation (all ones without it):
+  // spatial hop ratios of the light-quark factorisation (nullptr: all ones):
   // direction k = 1, 2, 3 at offset 4 (L1 + .. + L_{k-1}), four tables of L_k
   // entries each: fwd[x_k] = a_k(x_k)/a_k(x_k+1), bwd[x_k] = a_k(x_k)/a_k(x_k-1)
   // (periodic), then the same for 1/a_k (the adjoint)

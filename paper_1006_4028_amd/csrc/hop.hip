@@ -119,18 +119,13 @@ template <int P, int MU, int NS, bool DAG>
 __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], const bool (&on)[NS], int i,
                                         const int (&x)[4],
                                         const typename Tr<P>::R (&cf)[NS], const typename Tr<P>::R (&cb)[NS],
-                                        cx<typename Tr<P>::R> (&acc)[NS][12]) {
+                                        const typename Tr<P>::R (&sp)[6], cx<typename Tr<P>::R> (&acc)[NS][12]) {
   using R = typename Tr<P>::R;
   constexpr int S = DAG ? -1 : 1;
   const Geom& g = a.g;
   const int L = MU == 0 ? g.T : MU == 1 ? g.L1 : MU == 2 ? g.L2 : g.L3;
   // spatial ratios of the light-quark factorisation (the time ones are per slot)
-  R sf = R(1), sb = R(1);
-  if constexpr (MU != 0) {
-    const double* t = a.sratio + (MU == 1 ? 0 : MU == 2 ? 4 * g.L1 : 4 * (g.L1 + g.L2));
-    sf = (R)t[(DAG ? 2 * L : 0) + x[MU]];
-    sb = (R)t[(DAG ? 3 * L : L) + x[MU]];
-  }
+  const R sf = MU == 0 ? R(1) : sp[2 * MU - 2], sb = MU == 0 ? R(1) : sp[2 * MU - 1];
   int y[4] = {x[0], x[1], x[2], x[3]};
   cx<R> psi[12], u[9];
   Half<R> h, w;
@@ -260,10 +255,22 @@ __device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool
     for (int k = 0; k < NS; ++k)
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[k][c] = cx<R>{R(0), R(0)};
-    hop_dir<P, 0, NS, DAG>(a, sl, on, i, x, cf, cb, acc);
-    hop_dir<P, 1, NS, DAG>(a, sl, on, i, x, cf, cb, acc);
-    hop_dir<P, 2, NS, DAG>(a, sl, on, i, x, cf, cb, acc);
-    hop_dir<P, 3, NS, DAG>(a, sl, on, i, x, cf, cb, acc);
+    // spatial ratios of the light-quark factorisation: fwd, bwd per direction
+    R sp[6] = {R(1), R(1), R(1), R(1), R(1), R(1)};
+    if (a.sratio) {  // uniform over the launch
+      const int Ls[3] = {g.L1, g.L2, g.L3};
+      int off = 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        sp[2 * k] = (R)a.sratio[off + (DAG ? 2 * Ls[k] : 0) + x[k + 1]];
+        sp[2 * k + 1] = (R)a.sratio[off + (DAG ? 3 * Ls[k] : Ls[k]) + x[k + 1]];
+        off += 4 * Ls[k];
+      }
+    }
+    hop_dir<P, 0, NS, DAG>(a, sl, on, i, x, cf, cb, sp, acc);
+    hop_dir<P, 1, NS, DAG>(a, sl, on, i, x, cf, cb, sp, acc);
+    hop_dir<P, 2, NS, DAG>(a, sl, on, i, x, cf, cb, sp, acc);
+    hop_dir<P, 3, NS, DAG>(a, sl, on, i, x, cf, cb, sp, acc);
 #pragma unroll
     for (int k = 0; k < NS; ++k)
       if (on[k]) epilogue<P, EPI, RED, NT>(a, sl[k], i, acc[k], red[k]);

@@ -210,7 +210,8 @@ int timing_harvest(dp_ctx* c);
 // spatial tables of the light-quark factorisation (see dp_ctx::space)
 int upload_space(dp_ctx* c, const double* const a[3]);
 const double* space_ratios(dp_ctx* c, int variant);
-const double* space_profile(dp_ctx* c);  // nullptr without spatial profiles
+const double* space_profile(dp_ctx* c);     // nullptr without spatial profiles
+const double* space_hop_ratios(dp_ctx* c);  // nullptr without spatial profiles
 SlotTable slot_table(Workspace& w, int T, int s0, int prec, const int* mask);
 
 // launch helpers over slots [s0, s0 + n) of a workspace

@@ -120,6 +120,8 @@ const double* space_ratios(dp_ctx* c, int variant) {
   return c->space.as<double>() + (size_t)variant * 5 * (g.L1 + g.L2 + g.L3);
 }
 
+const double* space_hop_ratios(dp_ctx* c) { return c->has_space ? space_ratios(c, 1) : nullptr; }
+
 const double* space_profile(dp_ctx* c) {
   const Geom& g = c->g;
   return c->has_space ? space_ratios(c, 1) + 4 * (g.L1 + g.L2 + g.L3) : nullptr;
@@ -347,7 +349,7 @@ int hop(dp_ctx* c, Workspace& w, int s0, int n, int prec, int p, int dag, int ep
   a.clov.data = prec == F64 ? c->C64[p].p : prec == F32 ? c->C32[p].p : c->C16[p].p;
   a.clov.scale = prec == F16 ? c->C16s[p].as<float>() : nullptr;
   a.slots = slot_table(w, c->g.T, s0, prec, mask);
-  a.sratio = w.sratio ? w.sratio : space_ratios(c, 1);
+  a.sratio = w.sratio;
   a.red = reduce_ref(w, s0, red, fin, inner_mask);
   if (wv) a.red.w = wv->ref(s0);
   a.nslots = n;
@@ -664,7 +666,7 @@ int apply_core(dp_ctx* c, const double2* in, double2* out, int n, int flags) {
   const int dag = (flags & DP_DAGGER) ? 1 : 0;
   Workspace& w = c->ws_apply;
   DP_TRY(ensure_ws(c, w, n, prec));
-  w.sratio = space_ratios(c, (flags & DP_PRECOND) ? 1 : 0);
+  w.sratio = (flags & DP_PRECOND) && c->has_space ? space_ratios(c, 1) : nullptr;
   MassEntry* me = nullptr;
   DP_TRY(mass_entry(c, c->M, &me));
   const Geom& g = c->g;

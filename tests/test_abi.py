@@ -50,3 +50,18 @@ def test_binding_has_no_fallback(tmp_path, monkeypatch):
     monkeypatch.setattr(L, "_lib", None)
     with pytest.raises(ImportError):
         L.lib()
+
+
+def test_hop_kernels_do_not_spill():
+    """The compiler's resource report of the last build: no hop kernel
+    instantiation spills registers to scratch memory (a spill made the FP64
+    even-site kernel twice as slow once; the build records the report)."""
+    import json
+    path = os.path.join(ROOT, "paper_1006_4028_amd", "_build", "kernel_resources.json")
+    if not os.path.exists(path):
+        pytest.skip("no build report (run paper_1006_4028_amd/build.py)")
+    res = json.load(open(path))
+    hops = {k: v for k, v in res.items() if "hop_kernel" in k}
+    assert hops
+    spill = {k: v for k, v in hops.items() if v.get("scratch", 0) > 0}
+    assert not spill, spill
