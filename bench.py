@@ -128,7 +128,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=40,
                     help="requests in the served stream (0 skips the serving measurement)")
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the stream, 1/s")
+    ap.add_argument("--serve-rate", type=float, default=5.0,
+                    help="Poisson arrival rate of the stream, 1/s (5/s is about 0.8 of the FP64-inner capacity)")
     ap.add_argument("--no-dslash", action="store_true", help="skip the operator (Dslash) benchmark")
     ap.add_argument("--dslash-calls", type=int, default=100, help="timed operator calls per case")
     ap.add_argument("--pmc-probe", action="store_true", help="run the counter probe (under rocprofv3 --pmc)")

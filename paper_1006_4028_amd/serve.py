@@ -205,3 +205,55 @@ def summarize(server, reqs):
                 failed=sum(q.status == "failed" for q in reqs), solves=cols, seconds=span,
                 solves_per_s=cols / span if span > 0 else 0.0, p50_ms=float(np.percentile(lat, 50) * 1e3),
                 p99_ms=float(np.percentile(lat, 99) * 1e3), mean_slot_occupancy=float(np.mean(occ)) if occ else 0.0)
+
+
+def sweep(loads=(0.5, 0.8, 1.0, 1.2), requests=150, r=1e-10, seed=2024, nslots=24, out=None):
+    """The served-stream measurement: resident 16^3x32 and 24^3x48 fields, the
+    FP64-inner capacity measured first (a saturating stream), then Poisson
+    streams at the given fractions of that capacity, FP32 and FP64 inner, each
+    reporting solves/s and p50/p99 latency.  Returns the list of records."""
+    import json
+    import synth
+    fields = {}
+    for name in ("su3_16c32", "su3_24c48"):
+        cfg = synth.config(name)
+        fields[name] = (cfg["dims"], synth.gauge_su3(cfg["dims"], cfg["eps"], cfg["seed"]), cfg["csw"])
+    T_of = {k: v[0][0] for k, v in fields.items()}
+    recs = []
+
+    def run(prec, rate, n):
+        reqs = poisson_requests(n, rate, fields, T_of, seed=seed)
+        srv = Server(fields, nslots=nslots, precision=prec, r=r, max_iter=20000, k=4)
+        try:
+            s = summarize(srv, srv.run(reqs))
+        finally:
+            srv.close()
+        rec = dict(precision=prec, rate_per_s=rate, r=r, **s)
+        print(json.dumps(rec), flush=True)
+        if out:
+            out.write(json.dumps(rec) + "\n")
+            out.flush()
+        return rec
+
+    cap = run("f64", 1000.0, max(40, requests // 3))  # every request at once: the capacity
+    mean_cols = cap["solves"] / max(cap["done"], 1)
+    cap_req = cap["solves_per_s"] / mean_cols
+    recs.append(dict(cap, kind="capacity"))
+    for f in loads:
+        for prec in ("f32", "f64"):
+            rec = run(prec, f * cap_req, requests)
+            rec["load"] = f
+            recs.append(rec)
+    return recs
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="served-stream load sweep (one GPU)")
+    ap.add_argument("--requests", type=int, default=150)
+    ap.add_argument("--r", type=float, default=1e-10)
+    ap.add_argument("--loads", default="0.5,0.8,1.0,1.2")
+    ap.add_argument("--out", default=None, help="also append the JSON records to this file")
+    a = ap.parse_args()
+    f = open(a.out, "a") if a.out else None
+    sweep(tuple(float(x) for x in a.loads.split(",")), a.requests, a.r, out=f)
