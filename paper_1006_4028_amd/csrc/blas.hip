@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
   const int slot = blockIdx.y;
   if (a.mask && !a.mask[slot]) return;  // uniform over the slot's blocks
   const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  const int Vh = g.Vh;
+  const int Vh = g.Vh, Vp = g.Vp;
   double red[4] = {0.0, 0.0, 0.0, 0.0};
   int nv = 0;
   if constexpr (OP == OP_BICG_INIT || OP == OP_CG_XR || OP == OP_SUB64 || OP == OP_NORM) nv = 1;
@@ -45,46 +45,46 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
     if constexpr (OP == OP_ZERO) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) A[c] = z{0.0, 0.0};
-      st<P>(a.v[0], slot, i, Vh, A);
+      st<P>(a.v[0], slot, i, Vp, A);
     } else if constexpr (OP == OP_COPY) {
-      ld<P>(a.v[1], slot, i, Vh, A);
-      st<P>(a.v[0], slot, i, Vh, A);
+      ld<P>(a.v[1], slot, i, Vp, A);
+      st<P>(a.v[0], slot, i, Vp, A);
     } else if constexpr (OP == OP_BICG_INIT) {
-      ld<P>(a.v[1], slot, i, Vh, A);
-      st<P>(a.v[0], slot, i, Vh, A);
+      ld<P>(a.v[1], slot, i, Vp, A);
+      st<P>(a.v[0], slot, i, Vp, A);
       red[0] = norm2(A);
 #pragma unroll
       for (int c = 0; c < 12; ++c) B[c] = z{0.0, 0.0};
-      st<P>(a.v[2], slot, i, Vh, B);
-      st<P>(a.v[3], slot, i, Vh, B);
-      st<PX>(a.v[4], slot, i, Vh, B);
+      st<P>(a.v[2], slot, i, Vp, B);
+      st<P>(a.v[3], slot, i, Vp, B);
+      st<PX>(a.v[4], slot, i, Vp, B);
     } else if constexpr (OP == OP_BICG_P) {
       const SlotScalars& s = a.sc[slot];
       const z beta{s.beta[0], s.beta[1]}, omega{s.omega[0], s.omega[1]};
-      ld<P>(a.v[0], slot, i, Vh, A);  // p
-      ld<P>(a.v[1], slot, i, Vh, B);  // r
-      ld<P>(a.v[2], slot, i, Vh, C);  // v
+      ld<P>(a.v[0], slot, i, Vp, A);  // p
+      ld<P>(a.v[1], slot, i, Vp, B);  // r
+      ld<P>(a.v[2], slot, i, Vp, C);  // v
 #pragma unroll
       for (int c = 0; c < 12; ++c) A[c] = B[c] + cmul(beta, A[c] - cmul(omega, C[c]));
-      st<P>(a.v[0], slot, i, Vh, A);
+      st<P>(a.v[0], slot, i, Vp, A);
     } else if constexpr (OP == OP_BICG_S) {
       const SlotScalars& s = a.sc[slot];
       const z alpha{s.alpha[0], s.alpha[1]};
-      ld<P>(a.v[1], slot, i, Vh, B);  // r
-      ld<P>(a.v[2], slot, i, Vh, C);  // v
+      ld<P>(a.v[1], slot, i, Vp, B);  // r
+      ld<P>(a.v[2], slot, i, Vp, C);  // v
 #pragma unroll
       for (int c = 0; c < 12; ++c) A[c] = B[c] - cmul(alpha, C[c]);
-      st<P>(a.v[0], slot, i, Vh, A);
+      st<P>(a.v[0], slot, i, Vp, A);
     } else if constexpr (OP == OP_BICG_XR) {
       const SlotScalars& s = a.sc[slot];
       const z alpha{s.alpha[0], s.alpha[1]}, omega{s.omega[0], s.omega[1]};
       z D[12], E[12];
       // every load before the first store, so that they can all be in flight
-      ld<PX>(a.v[0], slot, i, Vh, A);  // x
-      ld<P>(a.v[1], slot, i, Vh, B);   // p
-      ld<P>(a.v[2], slot, i, Vh, C);   // s
-      ld<P>(a.v[4], slot, i, Vh, D);   // t
-      ld<P>(a.v[5], slot, i, Vh, E);   // rh
+      ld<PX>(a.v[0], slot, i, Vp, A);  // x
+      ld<P>(a.v[1], slot, i, Vp, B);   // p
+      ld<P>(a.v[2], slot, i, Vp, C);   // s
+      ld<P>(a.v[4], slot, i, Vp, D);   // t
+      ld<P>(a.v[5], slot, i, Vp, E);   // rh
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         A[c] = A[c] + cmul(alpha, B[c]) + cmul(omega, C[c]);
@@ -94,55 +94,55 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
         red[1] += d.y;
       }
       red[2] = norm2(C);
-      st<PX>(a.v[0], slot, i, Vh, A);
-      st<P>(a.v[3], slot, i, Vh, C);
+      st<PX>(a.v[0], slot, i, Vp, A);
+      st<P>(a.v[3], slot, i, Vp, C);
     } else if constexpr (OP == OP_CG_XR) {
       const double ca = a.sc[slot].cg_a;
       z D[12];
-      ld<PX>(a.v[0], slot, i, Vh, A);  // x
-      ld<P>(a.v[1], slot, i, Vh, B);   // p
-      ld<P>(a.v[2], slot, i, Vh, C);   // r
-      ld<P>(a.v[3], slot, i, Vh, D);   // w
+      ld<PX>(a.v[0], slot, i, Vp, A);  // x
+      ld<P>(a.v[1], slot, i, Vp, B);   // p
+      ld<P>(a.v[2], slot, i, Vp, C);   // r
+      ld<P>(a.v[3], slot, i, Vp, D);   // w
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         A[c] = A[c] + ca * B[c];
         C[c] = C[c] - ca * D[c];
       }
       red[0] = norm2(C);
-      st<PX>(a.v[0], slot, i, Vh, A);
-      st<P>(a.v[2], slot, i, Vh, C);
+      st<PX>(a.v[0], slot, i, Vp, A);
+      st<P>(a.v[2], slot, i, Vp, C);
     } else if constexpr (OP == OP_CG_P) {
       const double cb = a.sc[slot].cg_b;
-      ld<P>(a.v[0], slot, i, Vh, A);  // p
-      ld<P>(a.v[1], slot, i, Vh, B);  // z
+      ld<P>(a.v[0], slot, i, Vp, A);  // p
+      ld<P>(a.v[1], slot, i, Vp, B);  // z
 #pragma unroll
       for (int c = 0; c < 12; ++c) A[c] = B[c] + cb * A[c];
-      st<P>(a.v[0], slot, i, Vh, A);
+      st<P>(a.v[0], slot, i, Vp, A);
     } else if constexpr (OP == OP_SCALE_COPY) {
       const double f = a.slot_scale[slot];
-      ld<F64>(a.v[1], slot, i, Vh, B);
+      ld<F64>(a.v[1], slot, i, Vp, B);
 #pragma unroll
       for (int c = 0; c < 12; ++c) A[c] = f * B[c];
-      st<P>(a.v[0], slot, i, Vh, A);
+      st<P>(a.v[0], slot, i, Vp, A);
     } else if constexpr (OP == OP_AXPY_SCALED) {
       const double f = a.slot_scale[slot];
-      ld<F64>(a.v[0], slot, i, Vh, A);
-      ld<PX>(a.v[1], slot, i, Vh, B);
+      ld<F64>(a.v[0], slot, i, Vp, A);
+      ld<PX>(a.v[1], slot, i, Vp, B);
 #pragma unroll
       for (int c = 0; c < 12; ++c) A[c] = A[c] + f * B[c];
-      st<F64>(a.v[0], slot, i, Vh, A);
+      st<F64>(a.v[0], slot, i, Vp, A);
     } else if constexpr (OP == OP_SUB64) {
-      ld<F64>(a.v[1], slot, i, Vh, B);
-      ld<F64>(a.v[2], slot, i, Vh, C);
+      ld<F64>(a.v[1], slot, i, Vp, B);
+      ld<F64>(a.v[2], slot, i, Vp, C);
 #pragma unroll
       for (int c = 0; c < 12; ++c) A[c] = B[c] - C[c];
-      st<F64>(a.v[0], slot, i, Vh, A);
+      st<F64>(a.v[0], slot, i, Vp, A);
       red[0] = norm2(A);
     } else if constexpr (OP == OP_TO64) {
-      ld<P>(a.v[1], slot, i, Vh, B);
-      st<F64>(a.v[0], slot, i, Vh, B);
+      ld<P>(a.v[1], slot, i, Vp, B);
+      st<F64>(a.v[0], slot, i, Vp, B);
     } else if constexpr (OP == OP_NORM) {
-      ld<P>(a.v[1], slot, i, Vh, B);
+      ld<P>(a.v[1], slot, i, Vp, B);
       red[0] = norm2(B);
     }
   }

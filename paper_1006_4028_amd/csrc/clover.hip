@@ -26,11 +26,11 @@ __device__ __forceinline__ M3 load_link64(const Geom& g, const double2* const* U
                                           int mu) {
   const int p = (x0 + x1 + x2 + x3) & 1;
   const int i = eo_index(g, x0, x1, x2, x3);
-  const double2* b = U[p] + (long)mu * 9 * g.Vh;
+  const double2* b = U[p] + (long)mu * 9 * g.Vp;
   M3 r;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    const double2 v = b[(long)k * g.Vh + i];
+    const double2 v = b[(long)k * g.Vp + i];
     r.m[k] = z{v.x, v.y};
   }
   return r;
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(128) clover_build_kernel(Geom g, const double2
         A[a][3 + b] = f * ti(G1 - ti(G2));
         A[3 + a][b] = f * ti(G1 + ti(G2));
       }
-    store_block(dst, g.Vh, i, h, A);
+    store_block(dst, g.Vp, i, h, A);
   }
 }
 
@@ -199,7 +199,7 @@ __global__ void clover_pack_kernel(Geom g, const double2* __restrict__ C, double
         const double2 v = c[(6 * h + r) * 12 + 6 * h + q];
         A[r][q] = z{v.x, v.y};
       }
-    store_block(p ? Co : Ce, g.Vh, (int)(s >> 1), h, A);
+    store_block(p ? Co : Ce, g.Vp, (int)(s >> 1), h, A);
   }
 }
 
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(128) clover_invert_kernel(Geom g, const double
   const int h = blockIdx.y;
   if (i >= g.Vh) return;
   z A[6][6], X[6][6];
-  load_block(C, g.Vh, i, h, A);
+  load_block(C, g.Vp, i, h, A);
   for (int r = 0; r < 6; ++r) {
     A[r][r].x += m4;
     for (int c = 0; c < 6; ++c) X[r][c] = z{r == c ? 1.0 : 0.0, 0.0};
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(128) clover_invert_kernel(Geom g, const double
     X[r][r] = z{X[r][r].x, 0.0};
     for (int c = r + 1; c < 6; ++c) X[r][c] = z{0.5 * (X[r][c].x + X[c][r].x), 0.5 * (X[r][c].y - X[c][r].y)};
   }
-  store_block(Ainv, g.Vh, i, h, X);
+  store_block(Ainv, g.Vp, i, h, X);
 }
 
 template <int P>
@@ -260,14 +260,14 @@ __global__ void clover_convert_kernel(Geom g, const double2* __restrict__ C, voi
   if (i >= g.Vh) return;
   double r[72];
   for (int k = 0; k < 36; ++k) {
-    const double2 v = C[(long)k * g.Vh + i];
+    const double2 v = C[(long)k * g.Vp + i];
     r[2 * k] = v.x;
     r[2 * k + 1] = v.y;
   }
   if constexpr (P == F32) {
     float4* o = static_cast<float4*>(out);
     for (int k = 0; k < 18; ++k)
-      o[(long)k * g.Vh + i] = make_float4((float)r[4 * k], (float)r[4 * k + 1], (float)r[4 * k + 2], (float)r[4 * k + 3]);
+      o[(long)k * g.Vp + i] = make_float4((float)r[4 * k], (float)r[4 * k + 1], (float)r[4 * k + 2], (float)r[4 * k + 3]);
   } else {
     double m = 0.0;
     for (int k = 0; k < 72; ++k) m = fmax(m, fabs(r[k]));
@@ -280,7 +280,7 @@ __global__ void clover_convert_kernel(Geom g, const double2* __restrict__ C, voi
       v.y = f2h((float)(r[8 * k + 2] * inv), (float)(r[8 * k + 3] * inv));
       v.z = f2h((float)(r[8 * k + 4] * inv), (float)(r[8 * k + 5] * inv));
       v.w = f2h((float)(r[8 * k + 6] * inv), (float)(r[8 * k + 7] * inv));
-      o[(long)k * g.Vh + i] = v;
+      o[(long)k * g.Vp + i] = v;
     }
   }
 }
@@ -291,12 +291,12 @@ __global__ void clover_apply_kernel(Geom g, SlotTable slots, SpinorRef in, Spino
   const int slot = blockIdx.y;
   if (i >= g.Vh || (slots.mask && !slots.mask[slot])) return;
   z a[12], b[12];
-  SpinorIO<F64>::load(in, slot, i, g.Vh, a);
+  SpinorIO<F64>::load(in, slot, i, g.Vp, a);
   HermBlock<double> B[2];
-  CloverIO<F64>::load(slots.ainv[slot], nullptr, i, g.Vh, B);
+  CloverIO<F64>::load(slots.ainv[slot], nullptr, i, g.Vp, B);
   herm_apply(B[0], 0.0, &a[0], &b[0]);
   herm_apply(B[1], 0.0, &a[6], &b[6]);
-  SpinorIO<F64>::store(out, slot, i, g.Vh, b);
+  SpinorIO<F64>::store(out, slot, i, g.Vp, b);
 }
 
 }  // namespace

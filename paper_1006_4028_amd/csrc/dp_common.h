@@ -34,6 +34,7 @@ struct Geom {
   int L3h;  // L3 / 2
   int Vsh;  // sites of one parity in one timeslice
   int Vh;   // sites of one parity
+  int Vp;   // component stride of every structure-of-arrays field (Vh padded)
 };
 
 // Bytes of one site of one parity in each storage format.

@@ -132,11 +132,11 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
   // forward neighbour x + mu
   y[MU] = x[MU] + 1 == L ? 0 : x[MU] + 1;
   const int jf = eo_index(g, y[0], y[1], y[2], y[3]);
-  LinkIO<P>::load(a.U_out, MU, i, g.Vh, u);
+  LinkIO<P>::load(a.U_out, MU, i, g.Vp, u);
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     if (on[k]) {
-      const R sc = SpinorIO<P>::load_unscaled(a.in, sl[k], jf, g.Vh, psi);
+      const R sc = SpinorIO<P>::load_unscaled(a.in, sl[k], jf, g.Vp, psi);
       project<MU, S>(psi, h);
       link_mul(u, h, w);
       accumulate<MU, S>(acc[k], w, (MU == 0 ? cf[k] : sf) * sc);
@@ -145,11 +145,11 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
   // backward neighbour x - mu
   y[MU] = x[MU] == 0 ? L - 1 : x[MU] - 1;
   const int jb = eo_index(g, y[0], y[1], y[2], y[3]);
-  LinkIO<P>::load(a.U_in, MU, jb, g.Vh, u);
+  LinkIO<P>::load(a.U_in, MU, jb, g.Vp, u);
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     if (on[k]) {
-      const R sc = SpinorIO<P>::load_unscaled(a.in, sl[k], jb, g.Vh, psi);
+      const R sc = SpinorIO<P>::load_unscaled(a.in, sl[k], jb, g.Vp, psi);
       project<MU, -S>(psi, h);
       link_dag_mul(u, h, w);
       accumulate<MU, -S>(acc[k], w, (MU == 0 ? cb[k] : sb) * sc);
@@ -166,14 +166,14 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
   const Geom& g = a.g;
   cx<R> out[12], xin[12], wv[12];
   if constexpr (EPI == EPI_DIAG || EPI == EPI_SUB || EPI == EPI_INV_SUB)
-    SpinorIO<P>::template load<NT>(a.xin, slot, i, g.Vh, xin);
-  if constexpr (RED == RED_DOT_EXT) SpinorIO<P>::template load<NT>(a.red.w, slot, i, g.Vh, wv);
+    SpinorIO<P>::template load<NT>(a.xin, slot, i, g.Vp, xin);
+  if constexpr (RED == RED_DOT_EXT) SpinorIO<P>::template load<NT>(a.red.w, slot, i, g.Vp, wv);
   if constexpr (EPI == EPI_HOP) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) out[c] = R(-0.5) * acc[c];
   } else if constexpr (EPI == EPI_DIAG) {
     HermBlock<R> B[2];
-    CloverIO<P>::load(a.clov.data, a.clov.scale, i, g.Vh, B);
+    CloverIO<P>::load(a.clov.data, a.clov.scale, i, g.Vp, B);
     const R m4 = (R)a.slots.m4[slot];
     herm_apply(B[0], m4, &xin[0], &out[0]);
     herm_apply(B[1], m4, &xin[6], &out[6]);
@@ -194,11 +194,11 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
     }
     HermBlock<R> B[2];
     const float* sc = a.slots.ainv_scale ? a.slots.ainv_scale[slot] : nullptr;
-    CloverIO<P>::load(a.slots.ainv[slot], sc, i, g.Vh, B);
+    CloverIO<P>::load(a.slots.ainv[slot], sc, i, g.Vp, B);
     herm_apply(B[0], R(0), &t[0], &out[0]);
     herm_apply(B[1], R(0), &t[6], &out[6]);
   }
-  SpinorIO<P>::template store<NT>(a.out, slot, i, g.Vh, out);
+  SpinorIO<P>::template store<NT>(a.out, slot, i, g.Vp, out);
   if constexpr (RED == RED_DOT_EXT) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) {

@@ -39,7 +39,7 @@ __global__ void gauge_reorder_kernel(Geom g, const double2* __restrict__ U, void
   for (int mu = 0; mu < 4; ++mu)
     for (int k = 0; k < 9; ++k) {
       const double2 v = U ? U[(s * 4 + mu) * 9 + k] : make_double2((k % 4 == 0) ? 1.0 : 0.0, 0.0);
-      const long at = (long)(mu * 9 + k) * g.Vh + i;
+      const long at = (long)(mu * 9 + k) * g.Vp + i;
       if constexpr (P == F64) {
         static_cast<double2*>(dst)[at] = v;
       } else if constexpr (P == F32) {
@@ -64,7 +64,7 @@ __global__ void spinor_import_kernel(Geom g, const double2* __restrict__ aos, lo
   double2* d = static_cast<double2*>(dst.data) + slot * dst.slot_stride;
   for (int c = 0; c < 12; ++c) {
     const double2 v = src[c];
-    d[(long)c * g.Vh + i] = make_double2(f * v.x, f * v.y);
+    d[(long)c * g.Vp + i] = make_double2(f * v.x, f * v.y);
   }
 }
 
@@ -84,7 +84,7 @@ __global__ void spinor_export_kernel(Geom g, SpinorRef e, SpinorRef o, const dou
   const double inv = 1.0 / ((adiv ? adiv[(long)slot * g.T + x0] : 1.0) * space_factor(g, sprof, x1, x2, x3));
   double2* d = aos + slot * aos_ss + s * 12;
   for (int c = 0; c < 12; ++c) {
-    const double2 v = src[(long)c * g.Vh + i];
+    const double2 v = src[(long)c * g.Vp + i];
     d[c] = make_double2(v.x * inv, v.y * inv);
   }
 }
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(kBlock) cpp_kernel(Geom g, SpinorRef e, Spinor
       const int i = x0 * g.Vsh + k;
       double site = 0.0;
       for (int c = 0; c < 12; ++c) {
-        const double2 v = src[(long)c * g.Vh + i];
+        const double2 v = src[(long)c * g.Vp + i];
         site += v.x * v.x + v.y * v.y;
       }
       if (sprof) {

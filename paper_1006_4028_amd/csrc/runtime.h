@@ -200,6 +200,7 @@ int hip_fail(dp_ctx* c, hipError_t e, const char* expr, int line);
     if (rc_ != DP_OK) return rc_; \
   } while (0)
 
+bool env_pad();
 double now_s();
 void ratio_tables(int T, int bc_t, const double* alpha, double* out);
 int mass_entry(dp_ctx* c, double M, MassEntry** out);
