@@ -53,6 +53,9 @@ def _lib():
         lib.orc_apply_modified4.argtypes = [ip, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp, dp, dp]
         lib.orc_solve_beta.argtypes = [ip, ctypes.c_int, dp, dp, ctypes.c_double, dp, ctypes.c_int, dp,
                                        ctypes.c_double, ctypes.c_int, dp, dp, dp]
+        lib.orc_solve_sap.argtypes = [ip, ctypes.c_int, dp, dp, ctypes.c_double, dp, ip, dp, ctypes.c_double,
+                                      ctypes.c_int, dp, dp, dp]
+        lib.orc_sap_apply.argtypes = [ip, ctypes.c_int, dp, dp, ctypes.c_double, dp, ip, dp, dp]
         lib.orc_cpp.argtypes = [ip, ctypes.c_int, dp, ctypes.c_int, dp]
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         lib.orc_get_threads.restype = ctypes.c_int
@@ -207,6 +210,44 @@ def solve(U, C, M, eta, alpha=None, r=1e-13, solver="bicgstab", maxit=100000, bc
         raise OracleError(f"orc_solve failed with code {rc} after {int(info[0])} iterations")
     d = dict(iters=int(info[0]), relres_prec=float(info[1]), relres=float(info[2]), code=rc)
     return (S, Sp, d) if return_prec else (S, d)
+
+
+def _sap_par(block, ncy, nmr, nkv):
+    return (ctypes.c_int * 7)(*[int(b) for b in block], int(ncy), int(nmr), int(nkv))
+
+
+def solve_sap(U, C, M, eta, block, beta=None, ncy=5, nmr=4, nkv=16, r=1e-13, maxit=10000, bc_t=-1,
+              return_prec=False, allow_unconverged=False):
+    """Solve (D+M) S = eta with SAP+GCR (Schwarz blocks of extents `block`)
+    on the beta-preconditioned system.  Returns (S, info) or (S, S', info)."""
+    U = _c128(U)
+    eta = _c128(eta)
+    dims = U.shape[:4]
+    S = np.zeros_like(eta)
+    Sp = np.zeros_like(eta) if return_prec else None
+    info = np.zeros(3)
+    prof = None if beta is None else _profiles(dims, beta)
+    Cc = None if C is None else _c128(C)
+    rc = _lib().orc_solve_sap(_dims(dims), int(bc_t), _ptr(U), _ptr(Cc), float(M), _ptr(prof),
+                              _sap_par(block, ncy, nmr, nkv), _ptr(eta), float(r), int(maxit), _ptr(S), _ptr(Sp),
+                              _ptr(info))
+    if rc != ORC_OK and not (allow_unconverged and rc == ORC_ENOCONV):
+        raise OracleError(f"orc_solve_sap failed with code {rc} after {int(info[0])} iterations")
+    d = dict(iters=int(info[0]), relres_prec=float(info[1]), code=rc)
+    return (S, Sp, d) if return_prec else (S, d)
+
+
+def sap_apply(U, C, M, r, block, beta=None, ncy=5, nmr=4, bc_t=-1):
+    """One application of the SAP preconditioner to r."""
+    U = _c128(U)
+    r = _c128(r)
+    dims = U.shape[:4]
+    out = np.zeros_like(r)
+    prof = None if beta is None else _profiles(dims, beta)
+    Cc = None if C is None else _c128(C)
+    _check(_lib().orc_sap_apply(_dims(dims), int(bc_t), _ptr(U), _ptr(Cc), float(M), _ptr(prof),
+                                _sap_par(block, ncy, nmr, 1), _ptr(r), _ptr(out)), "orc_sap_apply")
+    return out
 
 
 def cpp(S, x0_src=0):

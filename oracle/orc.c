@@ -709,6 +709,225 @@ static int solve_prof(op_ctx *po, int solver, const double *eta, double rtol, in
     return st;
 }
 
+/*
+ * The Schwarz alternating procedure with GCR, the solver of the paper's
+ * light-quark iteration counts (Table 1; Luescher's domain-decomposition
+ * method, which the paper cites), on the beta-preconditioned operator D'.
+ *
+ * The lattice is cut into blocks of extents bs[mu] (an even number of blocks
+ * per direction) coloured by the parity of the block coordinates, so blocks
+ * that touch have different colours.  One SAP application M r:
+ *     psi = 0
+ *     ncy times, for colour 0 then colour 1:
+ *         rho = (r - D' psi) restricted to the blocks of that colour
+ *         nmr minimal-residual steps on every block of that colour, with the
+ *         block operator D'_B = P_B D' P_B (Dirichlet block boundaries):
+ *             a = D'_B rho,  w_B = <a, rho>_B / <a, a>_B,
+ *             psi += w_B rho,  rho -= w_B a
+ * (while rho vanishes off the colour, P_c D' rho on the colour's sites is
+ * exactly the direct sum of the block operators, since a block's neighbours
+ * have the other colour).  GCR solves D' x = eta with this preconditioner on
+ * the right: z_k = M r, w_k = D' z_k orthogonalised against the earlier w_j
+ * (coefficients c_jk, norms b_k), r -= <w_k, r> w_k; after nkv steps or at
+ * convergence x += sum_k a_k z_k with the triangular system of the c_jk and
+ * b_k, and r is recomputed as eta - D' x.  Iterations count M applications.
+ */
+typedef struct {
+    int bs[4];
+    int nb[4];
+    long nblocks;
+} blocking;
+
+static int setup_blocking(const lattice *g, const int bs[4], blocking *b)
+{
+    b->nblocks = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        if (bs[mu] < 1 || g->L[mu] % bs[mu]) return ORC_EINVAL;
+        b->bs[mu] = bs[mu];
+        b->nb[mu] = g->L[mu] / bs[mu];
+        if (b->nb[mu] % 2) return ORC_EINVAL; /* touching blocks must differ in colour */
+        b->nblocks *= b->nb[mu];
+    }
+    return ORC_OK;
+}
+
+static long block_of(const lattice *g, const blocking *b, long x, int *colour)
+{
+    int xc[4];
+    coords_of(g, x, xc);
+    long k = 0;
+    int sum = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        const int c = xc[mu] / b->bs[mu];
+        k = k * b->nb[mu] + c;
+        sum += c;
+    }
+    *colour = sum & 1;
+    return k;
+}
+
+/* nmr minimal-residual steps on the blocks of one colour: psi += sum w_B rho */
+static void sap_blocks(op_ctx *o, const blocking *b, const long *blk, const int *col, int colour, int nmr,
+                       cplx *rho, cplx *a, cplx *psi, cplx *num, double *den)
+{
+    const long V = o->g.V;
+    for (int k = 0; k < nmr; ++k) {
+        op_prec(o, rho, a);
+        for (long q = 0; q < b->nblocks; ++q) { num[q] = 0; den[q] = 0; }
+        for (long x = 0; x < V; ++x) {
+            if (col[x] != colour) continue;
+            cplx nm = 0;
+            double dn = 0;
+            for (int i = 0; i < 12; ++i) {
+                nm += conj(a[12 * x + i]) * rho[12 * x + i];
+                dn += creal(conj(a[12 * x + i]) * a[12 * x + i]);
+            }
+            num[blk[x]] += nm;
+            den[blk[x]] += dn;
+        }
+        for (long x = 0; x < V; ++x) {
+            if (col[x] != colour) continue;
+            const cplx w = den[blk[x]] > 0 ? num[blk[x]] / den[blk[x]] : 0;
+            for (int i = 0; i < 12; ++i) {
+                psi[12 * x + i] += w * rho[12 * x + i];
+                rho[12 * x + i] -= w * a[12 * x + i];
+            }
+        }
+    }
+}
+
+/* psi = M r */
+static void sap_apply(op_ctx *o, const blocking *b, const long *blk, const int *col, int ncy, int nmr,
+                      const cplx *r, cplx *psi, cplx *rho, cplx *a, cplx *num, double *den)
+{
+    const long n = 12 * o->g.V;
+    memset(psi, 0, sizeof(cplx) * n);
+    for (int cy = 0; cy < ncy; ++cy)
+        for (int colour = 0; colour < 2; ++colour) {
+            op_prec(o, psi, a);
+            for (long x = 0; x < o->g.V; ++x)
+                for (int i = 0; i < 12; ++i)
+                    rho[12 * x + i] = col[x] == colour ? r[12 * x + i] - a[12 * x + i] : 0;
+            sap_blocks(o, b, blk, col, colour, nmr, rho, a, psi, num, den);
+        }
+}
+
+static int sap_gcr(op_ctx *o, const blocking *b, int ncy, int nmr, int nkv, const cplx *eta, cplx *x,
+                   double rtol, int maxit, int *iters)
+{
+    const long V = o->g.V, n = 12 * V;
+    long *blk = malloc(sizeof(long) * V);
+    int *col = malloc(sizeof(int) * V);
+    cplx *r = malloc(sizeof(cplx) * n), *rho = malloc(sizeof(cplx) * n), *a = malloc(sizeof(cplx) * n);
+    cplx *z = malloc(sizeof(cplx) * n * nkv), *w = malloc(sizeof(cplx) * n * nkv);
+    cplx *num = malloc(sizeof(cplx) * b->nblocks), *cc = malloc(sizeof(cplx) * nkv * nkv);
+    cplx *gam = malloc(sizeof(cplx) * nkv), *al = malloc(sizeof(cplx) * nkv);
+    double *den = malloc(sizeof(double) * b->nblocks), *bn = malloc(sizeof(double) * nkv);
+    if (!blk || !col || !r || !rho || !a || !z || !w || !num || !cc || !gam || !al || !den || !bn) return ORC_ENOMEM;
+    for (long s = 0; s < V; ++s) blk[s] = block_of(&o->g, b, s, &col[s]);
+    memset(x, 0, sizeof(cplx) * n);
+    memcpy(r, eta, sizeof(cplx) * n);
+    const double target = rtol * sqrt(norm2(n, eta));
+    int it = 0, status = ORC_ENOCONV;
+    double rn = sqrt(norm2(n, r));
+    if (rn <= target) status = ORC_OK;
+    while (status != ORC_OK && it < maxit) {
+        int k = 0;
+        for (; k < nkv && it < maxit; ++k) {
+            cplx *zk = z + n * k, *wk = w + n * k;
+            sap_apply(o, b, blk, col, ncy, nmr, r, zk, rho, a, num, den);
+            op_prec(o, zk, wk);
+            ++it;
+            for (int j = 0; j < k; ++j) {
+                const cplx *wj = w + n * j;
+                const cplx c = dot(n, wj, wk);
+                cc[j * nkv + k] = c;
+                for (long i = 0; i < n; ++i) wk[i] -= c * wj[i];
+            }
+            bn[k] = sqrt(norm2(n, wk));
+            if (!(bn[k] > 0)) { status = ORC_EBREAK; break; }
+            for (long i = 0; i < n; ++i) wk[i] /= bn[k];
+            gam[k] = dot(n, wk, r);
+            for (long i = 0; i < n; ++i) r[i] -= gam[k] * wk[i];
+            rn = sqrt(norm2(n, r));
+            if (rn <= target) { ++k; break; }
+        }
+        if (status == ORC_EBREAK) break;
+        /* the coefficients of the z_k: upper-triangular solve */
+        for (int j = k - 1; j >= 0; --j) {
+            cplx s = gam[j];
+            for (int l = j + 1; l < k; ++l) s -= cc[j * nkv + l] * al[l];
+            al[j] = s / bn[j];
+        }
+        for (int j = 0; j < k; ++j)
+            for (long i = 0; i < n; ++i) x[i] += al[j] * z[n * j + i];
+        op_prec(o, x, a);
+        for (long i = 0; i < n; ++i) r[i] = eta[i] - a[i];
+        rn = sqrt(norm2(n, r));
+        if (rn <= target) status = ORC_OK;
+    }
+    *iters = it;
+    free(blk); free(col); free(r); free(rho); free(a); free(z); free(w); free(num); free(cc);
+    free(gam); free(al); free(den); free(bn);
+    return status;
+}
+
+/* Solve (D+M) S = eta with SAP+GCR on the beta-preconditioned system
+ * (prof4: NULL or the T + L1 + L2 + L3 profile values); par = {bs0..bs3,
+ * ncy, nmr, nkv}.  info as for orc_solve. */
+int orc_solve_sap(const int dims[4], int bc_t, const double *U, const double *C, double M, const double *prof4,
+                  const int par[7], const double *eta, double rtol, int maxit, double *S, double *Sp, double *info)
+{
+    op_ctx o;
+    blocking b;
+    if (setup(&o.g, dims, bc_t) != ORC_OK || split_profiles(&o.g, prof4, o.prof)) return ORC_EINVAL;
+    if (setup_blocking(&o.g, par, &b) != ORC_OK || par[4] < 1 || par[5] < 1 || par[6] < 1) return ORC_EINVAL;
+    init_gammas();
+    o.U = (const cplx *)U; o.C = (const cplx *)C; o.M = M;
+    const long n = 12 * o.g.V;
+    o.tmp = malloc(sizeof(cplx) * n);
+    cplx *ep = malloc(sizeof(cplx) * n), *xp = malloc(sizeof(cplx) * n), *res = malloc(sizeof(cplx) * n);
+    if (!o.tmp || !ep || !xp || !res) return ORC_ENOMEM;
+    scale_by_beta(&o.g, o.prof, 0, (const cplx *)eta, ep);
+    int iters = 0;
+    int st = sap_gcr(&o, &b, par[4], par[5], par[6], ep, xp, rtol, maxit, &iters);
+    op_prec(&o, xp, res);
+    for (long i = 0; i < n; ++i) res[i] = ep[i] - res[i];
+    const double en = sqrt(norm2(n, ep)), rn = sqrt(norm2(n, res));
+    if (Sp) memcpy(Sp, xp, n * sizeof(cplx));
+    scale_by_beta(&o.g, o.prof, 1, xp, (cplx *)S);
+    if (info) {
+        info[0] = iters;
+        info[1] = en > 0 ? rn / en : 0;
+        info[2] = 0;
+    }
+    free(o.tmp); free(ep); free(xp); free(res);
+    return st;
+}
+
+/* psi = M r (one SAP application), for checking the preconditioner */
+int orc_sap_apply(const int dims[4], int bc_t, const double *U, const double *C, double M, const double *prof4,
+                  const int par[7], const double *r, double *psi)
+{
+    op_ctx o;
+    blocking b;
+    if (setup(&o.g, dims, bc_t) != ORC_OK || split_profiles(&o.g, prof4, o.prof)) return ORC_EINVAL;
+    if (setup_blocking(&o.g, par, &b) != ORC_OK || par[4] < 1 || par[5] < 1) return ORC_EINVAL;
+    init_gammas();
+    o.U = (const cplx *)U; o.C = (const cplx *)C; o.M = M;
+    const long V = o.g.V, n = 12 * V;
+    o.tmp = malloc(sizeof(cplx) * n);
+    long *blk = malloc(sizeof(long) * V);
+    int *col = malloc(sizeof(int) * V);
+    cplx *rho = malloc(sizeof(cplx) * n), *a = malloc(sizeof(cplx) * n), *num = malloc(sizeof(cplx) * b.nblocks);
+    double *den = malloc(sizeof(double) * b.nblocks);
+    if (!o.tmp || !blk || !col || !rho || !a || !num || !den) return ORC_ENOMEM;
+    for (long s = 0; s < V; ++s) blk[s] = block_of(&o.g, &b, s, &col[s]);
+    sap_apply(&o, &b, blk, col, par[4], par[5], (const cplx *)r, (cplx *)psi, rho, a, num, den);
+    free(o.tmp); free(blk); free(col); free(rho); free(a); free(num); free(den);
+    return ORC_OK;
+}
+
 /* C_PP(t) = - sum_{vec y} sum over the given columns of sum_{spin,colour} |S|^2,
  * t = (y0 - x0_src) mod T.  S: [ncols][V][12]. */
 int orc_cpp(const int dims[4], int ncols, const double *S_, int x0_src, double *cpp)
