@@ -173,6 +173,26 @@ int dp_solve(dp_ctx* ctx, const double* eta, int nrhs, const dp_params* p, doubl
 int dp_solve_dev(dp_ctx* ctx, const void* eta_dev, int nrhs, const dp_params* p, void* S_dev, double* cpp,
                  dp_info* info, void* hip_stream);
 
+/* SAP+GCR: the domain-decomposition solver of the paper's light-quark
+ * iteration counts (Table 1; the Schwarz alternating procedure it cites) on
+ * the preconditioned system with the ctx's mass, time profile and spatial
+ * profiles.  The lattice is cut into blocks of extents block[mu], each
+ * dividing its lattice extent an even number of times; one application of
+ * the preconditioner runs ncy cycles over the two block colours, each block
+ * solved by nmr minimal-residual steps with Dirichlet block boundaries in
+ * `precision` (DP_PREC_F32 or DP_PREC_F64); flexible GCR in FP64 with restart
+ * length nkv (1..64) runs until |eta' - D'S'| <= r |eta'| or max_iter
+ * preconditioner applications (info.iters; info.outer = restarts). */
+typedef struct {
+  double r;
+  int block[4];
+  int ncy, nmr, nkv;
+  int precision;
+  int max_iter;
+} dp_sap_params;
+/* One right-hand side (host layout); S and cpp (T doubles) nullable. */
+int dp_solve_sap(dp_ctx* ctx, const double* eta, const dp_sap_params* p, double* S, double* cpp, dp_info* info);
+
 /* Per-kernel timing of the library's own launches.  dp_set_timing(ctx, 1)
  * clears the statistics and brackets every later kernel launch of the ctx
  * with HIP events on the stream it runs on; dp_get_timing copies up to `max`

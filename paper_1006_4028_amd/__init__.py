@@ -188,6 +188,21 @@ class Lattice:
         self._check(rc, allow=(L.DP_ERR_NOT_CONVERGED,) if allow_unconverged else ())
         return S, cpp, self._infos(info)
 
+    def solve_sap(self, eta, block, r=1e-10, ncy=5, nmr=4, nkv=16, precision="f32", max_iter=1000,
+                  allow_unconverged=False):
+        """SAP+GCR for one right-hand side (host layout) with Schwarz blocks of
+        extents `block`; returns (S, cpp, info)."""
+        eta = _c128(eta)
+        assert eta.size == self.V * 12
+        S = np.zeros_like(eta)
+        cpp = np.zeros(self.T)
+        info = L.dp_info()
+        p = L.dp_sap_params(float(r), (ctypes.c_int * 4)(*[int(b) for b in block]), int(ncy), int(nmr), int(nkv),
+                            L.DP_PREC[precision], int(max_iter))
+        rc = self._L.dp_solve_sap(self._h, _ptr(eta), ctypes.byref(p), _ptr(S), _ptr(cpp), ctypes.byref(info))
+        self._check(rc, allow=(L.DP_ERR_NOT_CONVERGED,) if allow_unconverged else ())
+        return S, cpp, self._infos([info])[0]
+
     def solve_dev(self, eta_t, S_t=None, r=1e-11, solver="bicgstab", precision="f64", max_iter=10000, delta=0.0,
                   x0_src=0, ncols_group=0, allow_unconverged=False):
         """Device variant: eta_t (and S_t) are torch CUDA tensors in host layout."""

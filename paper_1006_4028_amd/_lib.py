@@ -30,11 +30,16 @@ DP_APPLY_SCHUR, DP_APPLY_F32, DP_APPLY_F16 = 8, 16, 32
 EXPORTED = [
     "dp_create", "dp_destroy", "dp_last_error", "dp_set_gauge", "dp_set_gauge_dev", "dp_set_clover",
     "dp_set_clover_field", "dp_set_mass", "dp_set_kappa", "dp_set_alpha", "dp_set_alpha_space", "dp_apply",
-    "dp_apply_dev", "dp_solve",
+    "dp_apply_dev", "dp_solve", "dp_solve_sap",
     "dp_solve_dev", "dp_footprint_bytes", "dp_set_timing", "dp_get_timing", "dp_get_timing_samples",
     "dp_batch_open", "dp_batch_close",
     "dp_batch_admit", "dp_batch_step", "dp_batch_harvest", "dp_batch_status", "dp_batch_device_bytes",
 ]
+
+
+class dp_sap_params(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_double), ("block", ctypes.c_int * 4), ("ncy", ctypes.c_int), ("nmr", ctypes.c_int),
+                ("nkv", ctypes.c_int), ("precision", ctypes.c_int), ("max_iter", ctypes.c_int)]
 
 
 class dp_params(ctypes.Structure):
@@ -97,6 +102,7 @@ def lib():
     L.dp_set_kappa.argtypes = [vp, ctypes.c_double]
     L.dp_set_alpha.argtypes = [vp, dp]
     L.dp_set_alpha_space.argtypes = [vp, dp, dp, dp]
+    L.dp_solve_sap.argtypes = [vp, dp, ctypes.POINTER(dp_sap_params), dp, dp, ctypes.POINTER(dp_info)]
     L.dp_apply.argtypes = [vp, dp, dp, ctypes.c_int]
     L.dp_apply_dev.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
     L.dp_solve.argtypes = [vp, dp, ctypes.c_int, ctypes.POINTER(dp_params), dp, dp, ctypes.POINTER(dp_info)]

@@ -84,6 +84,10 @@ struct MassEntry {
 };
 
 // Device work space of a set of slots at one inner precision.
+// Work space of the SAP+GCR solver (csrc/sap.hip), created on first use.
+struct SapState;
+void sap_free(SapState* s);
+
 struct Workspace {
   int nslots = 0, prec = -1;
   const double* sratio = nullptr;  // the ctx's spatial hop ratios these slots use
@@ -130,6 +134,7 @@ struct dp_ctx {
   dp::Workspace ws_apply;           // for dp_apply / dp_apply_dev
   std::vector<double> apply_key;    // what ws_apply's per-slot tables were built for
   dp_batch* solve_batch = nullptr;  // reused by dp_solve
+  dp::SapState* sap = nullptr;      // dp_solve_sap
   dp::DevBuf scratch_aos, bad_flag;
 
   // per-launch HIP-event timing of the library's kernels (dp_set_timing)

@@ -429,6 +429,7 @@ dp_ctx::~dp_ctx() {
   }
   for (auto e : ev_free) (void)hipEventDestroy(e);
   for (auto* m : masses) delete m;
+  dp::sap_free(sap);
   if (stream) (void)hipStreamDestroy(stream);
 }
 
