@@ -132,6 +132,8 @@ def main():
                     help="Poisson arrival rate of the stream, 1/s (5/s is about 0.8 of the FP64-inner capacity)")
     ap.add_argument("--no-dslash", action="store_true", help="skip the operator (Dslash) benchmark")
     ap.add_argument("--dslash-calls", type=int, default=100, help="timed operator calls per case")
+    ap.add_argument("--sap-study", action="store_true",
+                    help="SAP+GCR iteration counts vs alpha0 of the light-quark factorisation (one JSON line)")
     ap.add_argument("--pmc-probe", action="store_true", help="run the counter probe (under rocprofv3 --pmc)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="write the traffic record of the dominant kernel from two counter runs")
@@ -140,6 +142,8 @@ def main():
         return pmc_probe()
     if args.pmc_summary:
         return pmc_summary(*args.pmc_summary)
+    if args.sap_study:
+        return sap_study()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md on sharding)",
               file=sys.stderr)
@@ -275,6 +279,39 @@ def main():
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def sap_study():
+    """The analogue of the paper's Table 1 on the synthetic fields: SAP+GCR
+    iterations (and seconds) to invert the light-quark Dirac equation with the
+    four-direction cosh factorisation (eq. betaa) for alpha0 in {0, 0.2, 0.4};
+    48 x 24^3 with 6^4 blocks at r = 1e-11 (the D5 shape) and 64 x 32^3 with
+    4^4 blocks at r = 1e-10 (the E shape); M in {0.01, 0.05}; FP32 block
+    solves, ncy = 5, nmr = 4, nkv = 16; one point-source column."""
+    import paper_1006_4028_amd as dp
+    import synth
+    out = []
+    for name, block, r in (("su3_24c48", (6, 6, 6, 6), 1e-11), ("su3_32c64", (4, 4, 4, 4), 1e-10)):
+        cfg = synth.config(name)
+        dims = cfg["dims"]
+        U = synth.gauge_su3(dims, cfg["eps"], cfg["seed"])
+        L = dp.Lattice(dims)
+        L.set_gauge(U)
+        del U
+        L.set_clover(cfg["csw"])
+        eta = synth.point_sources_12(dims, (0, 0, 0, 0))[0]
+        for M in (0.01, 0.05):
+            L.set_mass(M)
+            for a0 in (0.0, 0.2, 0.4):
+                L.set_beta(synth.beta_cosh_paper(dims, a0))
+                _, _, info = L.solve_sap(eta, block, r=r, max_iter=2000)
+                rec = {"workload": name, "block": block, "r": r, "M": M, "alpha0": a0, "iters": info["iters"],
+                       "restarts": info["outer"], "seconds": round(info["seconds"], 3),
+                       "true_res": info["true_res"], "status": info["status"]}
+                log(json.dumps(rec))
+                out.append(rec)
+        L.close()
+    print(json.dumps({"sap_study": out}), flush=True)
 
 
 MALL_BYTES = 256 * 2 ** 20
