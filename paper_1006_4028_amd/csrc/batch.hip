@@ -455,8 +455,26 @@ static int validate_params(dp_ctx* c, int nrhs, const dp_params* p) {
   return DP_OK;
 }
 
+static int solve_batch(dp_ctx* c, const double2* eta, int n, const dp_params& P, double2* S, double* cpp_out,
+                       dp_info* info);
+
+// One batch filled with the columns of the request; after a failure other than
+// a column stopping at max_iter or going non-finite (both finish their slots)
+// the kept batch may hold slots that never finish, so it is dropped.
 static int solve_common(dp_ctx* c, const double2* eta, int n, const dp_params& P, double2* S, double* cpp_out,
                         dp_info* info) {
+  const int rc = solve_batch(c, eta, n, P, S, cpp_out, info);
+  if (rc != DP_OK && rc != DP_ERR_NOT_CONVERGED && rc != DP_ERR_NONFINITE && c->solve_batch) {
+    const std::string err = c->err;
+    dp_batch_close(c->solve_batch);
+    c->solve_batch = nullptr;
+    c->err = err;
+  }
+  return rc;
+}
+
+static int solve_batch(dp_ctx* c, const double2* eta, int n, const dp_params& P, double2* S, double* cpp_out,
+                       dp_info* info) {
   dp_batch*& b = c->solve_batch;
   if (b && (b->nslots < n || b->prec != P.precision || b->solver != P.solver)) {
     dp_batch_close(b);
