@@ -40,6 +40,12 @@
  *        C_PP(y0) = - sum_{vec y} tr[S^+(y) S(y)]
  *    (section on heavy quarks), indexed by t = (y0 - x0_src) mod T.
  *
+ * Time boundary of the fermion: antiperiodic, periodic, or Dirichlet (bc_t =
+ * 0: the field vanishes beyond the first and last timeslice, so the hops
+ * across the boundary drop; the fermion boundary of the Schroedinger
+ * functional with zero boundary fields, for which the paper used the
+ * exponential profile).
+ *
  * Layouts (complex128 interleaved, x0 slowest, x3 fastest):
  *   U[site][mu][a][b], psi[site][spin][colour], C[site][12][12]
  *   with row/column index 3*spin + colour.  dims = {T, L1, L2, L3}.
@@ -63,7 +69,7 @@ typedef double complex cplx;
 typedef struct {
     int L[4];
     long V;
-    int bc_t; /* +1 periodic, -1 antiperiodic in time for the fermion */
+    int bc_t; /* +1 periodic, -1 antiperiodic, 0 Dirichlet in time for the fermion */
 } lattice;
 
 /* ---------------------------------------------------------------- geometry */
@@ -100,7 +106,7 @@ static int setup(lattice *g, const int dims[4], int bc_t)
         if (dims[mu] < 1) return ORC_EINVAL;
         g->L[mu] = dims[mu];
     }
-    if (bc_t != 1 && bc_t != -1) return ORC_EINVAL;
+    if (bc_t != 1 && bc_t != -1 && bc_t != 0) return ORC_EINVAL;
     g->V = (long)dims[0] * dims[1] * dims[2] * dims[3];
     g->bc_t = bc_t;
     return ORC_OK;
@@ -323,10 +329,13 @@ static void dirac_nabla(const lattice *g, const cplx *U, const cplx *C, double M
             cplx back_psi[12], back_d[12], ds[12], lap[12];
             colour_mul(link(U, xm, mu), 1, in + 12 * xm, back_psi);
             colour_mul(link(U, xm, mu), 1, dpsi + 12 * xm, back_d);
+            /* Dirichlet time boundary: psi vanishes on the slice before x0 = 0, but
+             * its forward derivative there, U psi(x), does not; U^+ of it is psi(x) */
+            const int virt = mu == 0 && g->bc_t == 0 && xc[0] == 0;
             for (int i = 0; i < 12; ++i) {
                 cplx nab_star = in[12 * x + i] - b * back_psi[i];
                 ds[i] = dpsi[12 * x + i] + nab_star;           /* (nabla + nabla*) psi */
-                lap[i] = dpsi[12 * x + i] - b * back_d[i];     /* nabla*(nabla psi)     */
+                lap[i] = dpsi[12 * x + i] - (virt ? in[12 * x + i] : b * back_d[i]); /* nabla*(nabla psi) */
             }
             cplx *o = out + 12 * x;
             for (int s = 0; s < 4; ++s)
