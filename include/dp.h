@@ -105,7 +105,10 @@ typedef struct {
 } dp_info;
 
 /* Create a context on GPU `device` for a lattice dims = {T, L1, L2, L3}
- * (all even, >= 2), time boundary bc_t = -1 (antiperiodic) or +1 (periodic).
+ * (all even, >= 2), time boundary bc_t = -1 (antiperiodic), +1 (periodic) or
+ * 0 (Dirichlet: the fermion vanishes beyond the first and last timeslice, the
+ * boundary of the Schroedinger functional with zero boundary fields; the
+ * clover term is built from the given links as everywhere else).
  * The state starts with unit links, c_sw = 0, M = 0 and alpha = 1. */
 int dp_create(const int dims[4], int bc_t, int device, dp_ctx** out);
 void dp_destroy(dp_ctx* ctx);

@@ -79,7 +79,8 @@ double now_s() {
 // ratio tables of the modified time hops for one alpha table:
 //   fwd[x0] = s_f alpha(x0)/alpha(x0+1), bwd[x0] = s_b alpha(x0)/alpha(x0-1),
 //   fwd_dag, bwd_dag the same for 1/alpha, with the fermion boundary sign s
-//   at the wrap-around (the boundary rule eq. redeftbc in ratio form).
+//   at the wrap-around (the boundary rule eq. redeftbc in ratio form); s = 0
+//   is the Dirichlet boundary, the hops across it drop.
 void ratio_tables(int T, int bc_t, const double* alpha, double* out) {
   for (int t = 0; t < T; ++t) {
     const int tp = (t + 1) % T, tm = (t - 1 + T) % T;
@@ -505,7 +506,7 @@ int dp_create(const int dims[4], int bc_t, int device, dp_ctx** out) {
   *out = nullptr;
   for (int k = 0; k < 4; ++k)
     if (dims[k] < 2 || dims[k] % 2) return DP_ERR_INVALID_ARG;
-  if (bc_t != 1 && bc_t != -1) return DP_ERR_INVALID_ARG;
+  if (bc_t != 1 && bc_t != -1 && bc_t != 0) return DP_ERR_INVALID_ARG;
   const long V = (long)dims[0] * dims[1] * dims[2] * dims[3];
   if (V / 2 > (1L << 30) / 12) return DP_ERR_INVALID_ARG;  // 32-bit indexing of the SoA fields
   int ndev = 0;

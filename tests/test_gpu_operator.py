@@ -25,7 +25,7 @@ def setup_field(dims, seed, csw=1.6, eps=0.6):
 
 
 @pytest.mark.parametrize("dims", DIMS)
-@pytest.mark.parametrize("bc_t", [-1, 1])
+@pytest.mark.parametrize("bc_t", [-1, 1, 0])
 def test_hop_only(dims, bc_t):
     log(f"test_hop_only dims={dims} bc_t={bc_t}")
     U, _, alpha = setup_field(dims, 100 + dims[1])
@@ -192,3 +192,23 @@ def test_light_quark_factorisation_operator(dims):
                 assert e < tol
         plain = oracle.apply(U, C, 0.25, psi)
         assert max_rel(L.apply(psi, precond=False), plain) < 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-6), ("f16", 3e-3)])
+def test_dirichlet_time_boundary_operator(precision, tol):
+    """The Dirichlet time boundary (bc_t = 0): full and Schur operators and
+    their adjoints against the oracle, every storage precision."""
+    dims = (8, 4, 6, 4)
+    log(f"test_dirichlet_time_boundary_operator {precision}")
+    U, C, alpha = setup_field(dims, 600)
+    psi = synth.random_spinor(dims, 14)
+    with lattice(dims, bc_t=0) as L:
+        L.set_gauge(U)
+        L.set_clover(1.6)
+        L.set_mass(0.3)
+        L.set_alpha(alpha)
+        for dagger in (False, True):
+            ref = oracle.apply(U, C, 0.3, psi, alpha=alpha, bc_t=0, dagger=dagger)
+            assert rel_err(L.apply(psi, precond=True, dagger=dagger, precision=precision), ref) < tol
+            refs = oracle_schur(oracle, U, C, 0.3, psi, alpha, bc_t=0, dagger=dagger)
+            assert rel_err(L.apply(psi, precond=True, schur=True, dagger=dagger, precision=precision), refs) < tol

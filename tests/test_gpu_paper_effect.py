@@ -42,3 +42,33 @@ def test_loose_residue_far_timeslices(precision):
     # preconditioned at the same residue: right everywhere, by orders of magnitude more
     assert e_prec.max() < 1e-4
     assert e_prec[far].max() < 1e-3 * e_plain[far].max()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_schroedinger_functional_boundary_loose_residue(precision):
+    """The closing remark of the heavy-quark section: with Schroedinger-
+    functional (Dirichlet) time boundaries the correlator decays over the
+    whole time extent, so far timeslices need tiny residues; the paper used
+    the exponential profile there.  Free field, 4^3 x 32, M = 0.5, source on
+    the first timeslice, r = 1e-6: without the profile the far timeslices are
+    wrong by percents, with alpha = exp(0.4 t) (the paper's exp(-alpha0 x0) in
+    this convention) every timeslice agrees with the oracle's solve at 1e-13."""
+    import oracle
+    dims, M, r = (32, 4, 4, 4), 0.5, 1e-6
+    log(f"test_schroedinger_functional_boundary_loose_residue {precision}")
+    U = synth.free_gauge(dims)
+    eta = synth.point_sources_12(dims, (0, 0, 0, 0))
+    exact = oracle.cpp(np.stack([oracle.solve(U, None, M, eta[c], r=1e-13, bc_t=0)[0] for c in range(12)]))
+    with lattice(dims, bc_t=0) as L:
+        L.set_mass(M)
+        L.set_alpha(np.ones(dims[0]))
+        _, c_plain, _ = L.solve(eta, r=r, precision=precision, ncols_group=12, want_S=False)
+        L.set_alpha(synth.alpha_exp(dims[0], 0.4))
+        _, c_prec, _ = L.solve(eta, r=r, precision=precision, ncols_group=12, want_S=False)
+    e_plain = np.abs(c_plain[0] / exact - 1)
+    e_prec = np.abs(c_prec[0] / exact - 1)
+    for k in range(0, dims[0], 4):
+        log(f"  {k:2d}  {abs(exact[k]):.3e}  {e_plain[k]:.3e}  {e_prec[k]:.3e}")
+    assert np.all(np.diff(-exact) < 0)  # decays over the whole extent
+    assert e_plain[-4:].max() > 1e-2
+    assert e_prec.max() < 1e-4
