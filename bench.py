@@ -227,6 +227,19 @@ def main():
                 "iters": [i["iters"] for i in infos64],
                 "mixed_vs_fp64_cpp_max_rel_err_per_timeslice": cpp_err}
         log(f"  {fp64['value']} solves/s; mixed/FP64 C_PP max rel err per timeslice {cpp_err:.2e}")
+        if args.precision == "f32":
+            # the lowest rung of the precision ladder, FP16 storage with per-site scales
+            log(f"FP16-storage inner path: 1 warmup + {args.steps} timed steps")
+            t16, lat16, infos16, cpp16, _ = run("f16", args.steps, 1)
+            for i in infos16:
+                assert i["status"] == 0 and i["true_res"] <= r, i
+            lat16_ms = sorted(1e3 * x for x in lat16)
+            fp64["f16_inner"] = {"value": round(ncols * args.steps / t16, 3), "unit": "solves/s",
+                                 "p50_ms": round(pct(lat16_ms, 0.5), 3), "p99_ms": round(pct(lat16_ms, 0.99), 3),
+                                 "iters": [i["iters"] for i in infos16],
+                                 "vs_fp64_cpp_max_rel_err_per_timeslice":
+                                     float(np.abs(cpp16[0] / cpp64[0] - 1).max())}
+            log(f"  {fp64['f16_inner']}")
 
     cpu = None
     if not args.no_cpu_baseline:
