@@ -106,7 +106,7 @@ def pmc_summary(fetch_csv, write_csv, command):
         out[key + "_scale"] = (1 << 20) / copy  # 1 GiB = 2^20 KiB moved by the copy
         out[key + "_launches"] = len(full)
     hbm = 1024 * (out["fetch_kib_per_launch"] * out["fetch_scale"] + out["write_kib_per_launch"] * out["write_scale"])
-    rec = {"kernel": "hop_f32_diag (hop_kernel_slab<1, 2, 1|2, 2>), 24^3x48, 12 slots", "command": command,
+    rec = {"kernel": "hop_f32_diag (hop_kernel_shared<1, 2, 1|2, 1>), 24^3x48, 12 slots", "command": command,
            "source_sha256": kernel_source_hash(), "hbm_bytes_per_launch": hbm, **out}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(rec, f, indent=1)

@@ -355,34 +355,44 @@ struct CloverIO<F64> {
     }
   }
 };
+// FP32 and FP16 blocks also load in two steps: the stored values as floats
+// (with the FP16 per-site scale; 1 for FP32), then the block assembled from
+// them.  A copy of the raw values (in LDS) assembled the same way gives
+// bitwise the same block and the same arithmetic after it.
 template <>
 struct CloverIO<F32> {
-  template <typename R>
-  __device__ static __forceinline__ void load(const void* base, const float*, int i, int Vh, HermBlock<R> (&B)[2]) {
+  __device__ static __forceinline__ float load_raw(const void* base, const float*, int i, int Vh, float (&r)[72]) {
     const float4* b = static_cast<const float4*>(base);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      float r[36];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const float4 v = b[(long)(h * 9 + k) * Vh + i];
-        r[4 * k] = v.x; r[4 * k + 1] = v.y; r[4 * k + 2] = v.z; r[4 * k + 3] = v.w;
-      }
-#pragma unroll
-      for (int k = 0; k < 6; ++k) B[h].d[k] = (R)r[k];
-#pragma unroll
-      for (int k = 0; k < 15; ++k) B[h].o[k] = cx<R>{(R)r[6 + 2 * k], (R)r[7 + 2 * k]};
+    for (int k = 0; k < 18; ++k) {
+      const float4 v = b[(long)k * Vh + i];
+      r[4 * k] = v.x; r[4 * k + 1] = v.y; r[4 * k + 2] = v.z; r[4 * k + 3] = v.w;
     }
+    return 1.f;
+  }
+  template <typename R>
+  __device__ static __forceinline__ void assemble(const float (&r)[72], float, HermBlock<R> (&B)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) B[h].d[k] = (R)r[36 * h + k];
+#pragma unroll
+      for (int k = 0; k < 15; ++k) B[h].o[k] = cx<R>{(R)r[36 * h + 6 + 2 * k], (R)r[36 * h + 7 + 2 * k]};
+    }
+  }
+  template <typename R>
+  __device__ static __forceinline__ void load(const void* base, const float* scale, int i, int Vh,
+                                              HermBlock<R> (&B)[2]) {
+    float r[72];
+    const float sc = load_raw(base, scale, i, Vh, r);
+    assemble(r, sc, B);
   }
 };
 template <>
 struct CloverIO<F16> {
-  template <typename R>
-  __device__ static __forceinline__ void load(const void* base, const float* scale, int i, int Vh,
-                                              HermBlock<R> (&B)[2]) {
+  __device__ static __forceinline__ float load_raw(const void* base, const float* scale, int i, int Vh,
+                                                   float (&r)[72]) {
     const uint4* b = static_cast<const uint4*>(base);
-    const float sc = scale[i];
-    float r[72];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       const uint4 v = b[(long)k * Vh + i];
@@ -390,6 +400,10 @@ struct CloverIO<F16> {
       r[8 * k + 0] = a0.x; r[8 * k + 1] = a0.y; r[8 * k + 2] = a1.x; r[8 * k + 3] = a1.y;
       r[8 * k + 4] = a2.x; r[8 * k + 5] = a2.y; r[8 * k + 6] = a3.x; r[8 * k + 7] = a3.y;
     }
+    return scale[i];
+  }
+  template <typename R>
+  __device__ static __forceinline__ void assemble(const float (&r)[72], float sc, HermBlock<R> (&B)[2]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -397,6 +411,13 @@ struct CloverIO<F16> {
 #pragma unroll
       for (int k = 0; k < 15; ++k) B[h].o[k] = cx<R>{(R)(r[36 * h + 6 + 2 * k] * sc), (R)(r[36 * h + 7 + 2 * k] * sc)};
     }
+  }
+  template <typename R>
+  __device__ static __forceinline__ void load(const void* base, const float* scale, int i, int Vh,
+                                              HermBlock<R> (&B)[2]) {
+    float r[72];
+    const float sc = load_raw(base, scale, i, Vh, r);
+    assemble(r, sc, B);
   }
 };
 

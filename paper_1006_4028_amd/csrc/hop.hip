@@ -115,11 +115,14 @@ __device__ __forceinline__ void link_dag_mul(const cx<R> (&u)[9], const Half<R>&
 // projectors at compile time (the signs then cost no arithmetic); an FP16
 // spinor's per-site scale multiplies the hop's coefficient instead of the 24
 // loaded components (the projection and the link product are linear).
-template <int P, int MU, int NS, bool DAG>
+// With LDS the links come from the workgroup's copy lu[8][9][64] (direction
+// 2 mu for the forward hop, 2 mu + 1 for the backward one; lane = site).
+template <int P, int MU, int NS, bool DAG, bool LDS>
 __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], const bool (&on)[NS], int i,
                                         const int (&x)[4],
                                         const typename Tr<P>::R (&cf)[NS], const typename Tr<P>::R (&cb)[NS],
-                                        const typename Tr<P>::R (&sp)[6], cx<typename Tr<P>::R> (&acc)[NS][12]) {
+                                        const typename Tr<P>::R (&sp)[6], cx<typename Tr<P>::R> (&acc)[NS][12],
+                                        const cx<typename Tr<P>::R>* lu, int lane) {
   using R = typename Tr<P>::R;
   constexpr int S = DAG ? -1 : 1;
   const Geom& g = a.g;
@@ -132,7 +135,12 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
   // forward neighbour x + mu
   y[MU] = x[MU] + 1 == L ? 0 : x[MU] + 1;
   const int jf = eo_index(g, y[0], y[1], y[2], y[3]);
-  LinkIO<P>::load(a.U_out, MU, i, g.Vp, u);
+  if constexpr (LDS) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = lu[((2 * MU) * 9 + k) * 64 + lane];
+  } else {
+    LinkIO<P>::load(a.U_out, MU, i, g.Vp, u);
+  }
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     if (on[k]) {
@@ -145,7 +153,12 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
   // backward neighbour x - mu
   y[MU] = x[MU] == 0 ? L - 1 : x[MU] - 1;
   const int jb = eo_index(g, y[0], y[1], y[2], y[3]);
-  LinkIO<P>::load(a.U_in, MU, jb, g.Vp, u);
+  if constexpr (LDS) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = lu[((2 * MU + 1) * 9 + k) * 64 + lane];
+  } else {
+    LinkIO<P>::load(a.U_in, MU, jb, g.Vp, u);
+  }
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     if (on[k]) {
@@ -159,9 +172,11 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
 
 // Epilogue and fused reduction terms for one slot.  NT marks the epilogue's
 // own inputs and the output as streamed (read or written once per launch).
-template <int P, int EPI, int RED, bool NT>
+// With LDS the clover blocks come from the workgroup's copy of the stored
+// values and scale, lc[73][64].
+template <int P, int EPI, int RED, bool NT, bool LDS>
 __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<typename Tr<P>::R> (&acc)[12],
-                                         double (&red)[4]) {
+                                         double (&red)[4], const float* lc, int lane) {
   using R = typename Tr<P>::R;
   const Geom& g = a.g;
   cx<R> out[12], xin[12], wv[12];
@@ -173,7 +188,14 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
     for (int c = 0; c < 12; ++c) out[c] = R(-0.5) * acc[c];
   } else if constexpr (EPI == EPI_DIAG) {
     HermBlock<R> B[2];
-    CloverIO<P>::load(a.clov.data, a.clov.scale, i, g.Vp, B);
+    if constexpr (LDS) {
+      float r[72];
+#pragma unroll
+      for (int k = 0; k < 72; ++k) r[k] = lc[k * 64 + lane];
+      CloverIO<P>::assemble(r, lc[72 * 64 + lane], B);
+    } else {
+      CloverIO<P>::load(a.clov.data, a.clov.scale, i, g.Vp, B);
+    }
     const R m4 = (R)a.slots.m4[slot];
     herm_apply(B[0], m4, &xin[0], &out[0]);
     herm_apply(B[1], m4, &xin[6], &out[6]);
@@ -221,8 +243,12 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
 // The work of one thread: the hop for output site i (if valid) and the active
 // slots of its group, the epilogue, and its share of the fused reductions
 // (stored as the partial `part` of `nparts` per slot).
-template <int P, int EPI, int RED, int NS, bool NT, bool DAG>
-__device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool valid, int part, int nparts) {
+// With LDS (one wave per slot group in a workgroup sharing links and clover)
+// each wave stores its own reduction partials.
+template <int P, int EPI, int RED, int NS, bool NT, bool DAG, bool LDS = false>
+__device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool valid, int part, int nparts,
+                                          const cx<typename Tr<P>::R>* lu = nullptr,
+                                          const float* lc = nullptr, int lane = 0) {
   using R = typename Tr<P>::R;
   const Geom& g = a.g;
   // active slots of the group (uniform over the block)
@@ -267,19 +293,30 @@ __device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool
         off += 4 * Ls[k];
       }
     }
-    hop_dir<P, 0, NS, DAG>(a, sl, on, i, x, cf, cb, sp, acc);
-    hop_dir<P, 1, NS, DAG>(a, sl, on, i, x, cf, cb, sp, acc);
-    hop_dir<P, 2, NS, DAG>(a, sl, on, i, x, cf, cb, sp, acc);
-    hop_dir<P, 3, NS, DAG>(a, sl, on, i, x, cf, cb, sp, acc);
+    hop_dir<P, 0, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
+    hop_dir<P, 1, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
+    hop_dir<P, 2, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
+    hop_dir<P, 3, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
 #pragma unroll
     for (int k = 0; k < NS; ++k)
-      if (on[k]) epilogue<P, EPI, RED, NT>(a, sl[k], i, acc[k], red[k]);
+      if (on[k]) epilogue<P, EPI, RED, NT, LDS>(a, sl[k], i, acc[k], red[k], lc, lane);
   }
   if constexpr (RED != RED_NONE) {
     constexpr int nv = RED == RED_DOT_EXT ? 2 : RED == RED_TS ? 3 : 1;
 #pragma unroll
-    for (int k = 0; k < NS; ++k)
-      if (on[k]) block_reduce_store(a.red, nv, red[k], sl[k], part, nparts);
+    for (int k = 0; k < NS; ++k) {
+      if (!on[k]) continue;
+      if constexpr (LDS) {
+        // the same sum as block_reduce_store over a 64-thread block
+        double* pt = a.red.partials + ((long)sl[k] * nparts + part) * 4;
+        for (int q = 0; q < nv; ++q) {
+          const double w = wave_sum(red[k][q]);
+          if (lane == 0) pt[q] = 0.0 + w;
+        }
+      } else {
+        block_reduce_store(a.red, nv, red[k], sl[k], part, nparts);
+      }
+    }
   }
 }
 
@@ -338,6 +375,78 @@ __global__ void __launch_bounds__(64) hop_kernel_slab(HopArgs a, SlabMap m) {
   site_work<P, EPI, RED, NS, NT, DAG>(a, grp, i, valid, (xcd * a.g.T + x0) * m.maxc + cl, 8 * a.g.T * m.maxc);
 }
 
+// Shared-tile mapping: the slab mapping's (XCD chunk, timeslice) with every
+// slot group in one workgroup (one wave per group).  The links of the chunk's
+// 64 sites in the 8 hop directions (and the clover blocks for the even-site
+// epilogue) are loaded once into LDS, converted to the arithmetic precision,
+// instead of once per slot group.  Per-slot arithmetic and reduction
+// partials are those of the slab mapping.
+template <int P>
+constexpr size_t shared_tile_bytes(bool clover) {
+  using R = typename Tr<P>::R;
+  return 8 * 9 * 64 * sizeof(cx<R>) + (clover ? 73 * 64 * sizeof(float) : 0);
+}
+
+// At most 8 waves per workgroup (256 VGPRs per lane); each wave takes slot
+// groups wv, wv + nw, ...
+template <int P, int EPI, int RED, int NS, bool NT, bool DAG>
+__global__ void __launch_bounds__(512) hop_kernel_shared(HopArgs a, SlabMap m) {
+  using R = typename Tr<P>::R;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<R>* lu = reinterpret_cast<cx<R>*>(smem);
+  float* lc = reinterpret_cast<float*>(smem + 8 * 9 * 64 * sizeof(cx<R>));
+  const Geom& g = a.g;
+  const int xcd = blockIdx.x & 7;
+  const int j = blockIdx.x >> 3;
+  const int cl = j % m.maxc, x0 = j / m.maxc;
+  const int chunk = slab_lo(m.nch, xcd) + cl;
+  const bool in_slab = chunk < slab_lo(m.nch, xcd + 1);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int sp = chunk * 64 + lane;
+  const bool valid = in_slab && sp < g.Vsh;
+  const int i = valid ? x0 * g.Vsh + sp : 0;
+  // fill: tasks 0..7 are the link directions (2 mu forward, 2 mu + 1 backward),
+  // task 8 the clover blocks; wave w takes tasks w, w + nw, ...
+  constexpr int ntask = EPI == EPI_DIAG ? 9 : 8;
+  if (valid) {
+    int x[4];
+    eo_coords(g, a.p, i, x[0], x[1], x[2], x[3]);
+#pragma unroll
+    for (int t = 0; t < ntask; ++t) {
+      if (t % nw != wv) continue;
+      if (t < 8) {
+        const int mu = t >> 1;  // a constant once unrolled
+        cx<R> u[9];
+        if ((t & 1) == 0) {
+          LinkIO<P>::load(a.U_out, mu, i, g.Vp, u);
+        } else {
+          int y[4] = {x[0], x[1], x[2], x[3]};
+          const int L = mu == 0 ? g.T : mu == 1 ? g.L1 : mu == 2 ? g.L2 : g.L3;
+          y[mu] = x[mu] == 0 ? L - 1 : x[mu] - 1;
+          LinkIO<P>::load(a.U_in, mu, eo_index(g, y[0], y[1], y[2], y[3]), g.Vp, u);
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) lu[(t * 9 + k) * 64 + lane] = u[k];
+      } else {
+        float r[72];
+        const float sc = CloverIO<P>::load_raw(a.clov.data, a.clov.scale, i, g.Vp, r);
+#pragma unroll
+        for (int k = 0; k < 72; ++k) lc[k * 64 + lane] = r[k];
+        lc[72 * 64 + lane] = sc;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int grp = wv; grp < m.ngroups; grp += nw) {
+    // keeps the compiler from hoisting the LDS reads out of this loop into
+    // (many) registers
+    asm volatile("" ::: "memory");
+    site_work<P, EPI, RED, NS, NT, DAG, true>(a, grp, i, valid, (xcd * g.T + x0) * m.maxc + cl, 8 * g.T * m.maxc, lu,
+                                              lc, lane);
+  }
+}
+
 int env_knob(const char* name, int dflt) {
   const char* e = getenv(name);
   return e ? atoi(e) : dflt;
@@ -388,6 +497,24 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
     // tuning knob: DP_HOP_LDS = bytes of (unused) LDS per block, which caps the
     // blocks resident per CU (160 KB of LDS per CU) and so the sweep front
     static const int lds = std::min(65536, std::max(0, env_knob("DP_HOP_LDS", 0)));
+    // FP32 with two or more slots: the shared-tile kernel, one slot per wave
+    // (measured on MI355X at 24^3x48 with 12 slots: 16% faster than the slab
+    // kernel with two slots per thread; in FP16 it was slower, the compiler
+    // then takes 250 registers per lane).  Tuning knob: DP_HOP_SHARED = 0
+    // keeps one workgroup per slot group.
+    static const bool shared = env_knob("DP_HOP_SHARED", 1) == 1;
+    if constexpr (P == F32) {
+      if (shared && nt && a.nslots >= 2 && !forced) {
+        m.ngroups = a.nslots;
+        // waves per workgroup: the fewest passes of at most 8 waves
+        const int passes = (a.nslots + 7) / 8;
+        const dim3 sgrid(nparts), sblock(64 * ((a.nslots + passes - 1) / passes));
+        hipLaunchKernelGGL((hop_kernel_shared<P, EPI, RED, 1, true, DAG>), sgrid, sblock,
+                           shared_tile_bytes<P>(EPI == EPI_DIAG), st, a, m);
+        *nparts_out = nparts;
+        return hipGetLastError();
+      }
+    }
     if (nt) {
       switch (ns) {
         case 2: hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 2, true, DAG>), grid, dim3(64), lds, st, a, m); break;
