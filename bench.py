@@ -131,7 +131,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=5.0,
                     help="Poisson arrival rate of the stream, 1/s (5/s is about 0.8 of the FP64-inner capacity)")
     ap.add_argument("--no-dslash", action="store_true", help="skip the operator (Dslash) benchmark")
-    ap.add_argument("--dslash-calls", type=int, default=100, help="timed operator calls per case")
+    ap.add_argument("--dslash-calls", type=int, default=200, help="timed operator calls per case")
     ap.add_argument("--sap-study", action="store_true",
                     help="SAP+GCR iteration counts vs alpha0 of the light-quark factorisation (one JSON line)")
     ap.add_argument("--pmc-probe", action="store_true", help="run the counter probe (under rocprofv3 --pmc)")
@@ -253,6 +253,22 @@ def main():
                "sample": f"1 of the {ncols} columns, full-lattice FP64 BiCGStab, {info_or['iters']} iterations, "
                          f"{t_or:.1f} s"}
         log(f"  {t_or:.1f} s for one column on {cpu['cores']} threads")
+        # the oracle's full-lattice operator on all threads and on one: links
+        # 144 + clover 72 + input 24 + output 24 reals per site, FP64
+        V = int(np.prod(dims))
+        nthr = oracle.get_threads()
+        cpu["operator"] = []
+        for n in (nthr, 1):
+            oracle.set_threads(n)
+            oracle.apply(U, C, M, eta[0], alpha=alpha)
+            t0 = time.perf_counter()
+            for _ in range(3):
+                oracle.apply(U, C, M, eta[0], alpha=alpha)
+            t_ap = (time.perf_counter() - t0) / 3
+            cpu["operator"].append({"threads": n, "ms": round(1e3 * t_ap, 1),
+                                    "GBps": round(V * 264 * 8 / t_ap / 1e9, 2)})
+            log(f"  oracle operator on {n} threads: {1e3 * t_ap:.1f} ms")
+        oracle.set_threads(nthr)
 
     traffic = measured_traffic()
     L.close()
@@ -345,6 +361,24 @@ def dslash_bench(args):
     import paper_1006_4028_amd as dp
     import synth
 
+    # a measured streaming rate beside the 8 TB/s specification: a 2 GiB
+    # device-to-device copy (read + write)
+    a = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ts = []
+    for _ in range(20):
+        ev[0].record()
+        b.copy_(a)
+        ev[1].record()
+        ev[1].synchronize()
+        ts.append(ev[0].elapsed_time(ev[1]) * 1e-3)
+    copy_gbs = 2 * a.numel() * 4 / float(np.median(ts)) / 1e9
+    del a, b
+    log(f"operator benchmark: device copy {copy_gbs:.0f} GB/s")
     out = []
     for name, a0 in (("su3_24c48", 0.4), ("su3_32c64", 0.1)):
         cfg = synth.config(name)
@@ -381,6 +415,8 @@ def dslash_bench(args):
                            "p90_us": round(float(np.percentile(us, 90)), 2),
                            "alg_bytes": b, "GBps": round(b / (med * 1e-6) / 1e9, 1),
                            "frac": round(b / (med * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                           "copy_GBps": round(copy_gbs, 1),
+                           "frac_of_copy": round(b / (med * 1e-6) / 1e9 / copy_gbs, 4),
                            "mall_resident": b < MALL_BYTES}
                     out.append(rec)
                     log(f"  {prec} nrhs={nrhs:2d} {k:14s} median {med:8.1f} us  {rec['GBps']:7.1f} GB/s "

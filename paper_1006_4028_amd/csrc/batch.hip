@@ -143,7 +143,20 @@ int inner_iteration(dp_batch* b) {
   Workspace& w = b->w;
   const int n = b->nslots, prec = b->prec;
   int* mi = w.mask_inner.as<int>();
-  if (b->solver == DP_SOLVER_BICGSTAB) {
+  // tuning knob: DP_BICG_FUSED = 0 takes rho from the stored residual and
+  // updates the search direction in a kernel of its own (one vector sweep
+  // more per iteration)
+  static const bool fused = [] {
+    const char* e = getenv("DP_BICG_FUSED");
+    return !(e && atoi(e) == 0);
+  }();
+  if (b->solver == DP_SOLVER_BICGSTAB && fused) {
+    // p enters as r after the start (and as the previous iteration's update)
+    DP_TRY(schur(c, w, 0, n, prec, 0, w.p, w.to, w.v, mi, RED_DOT_EXT, FIN_BICG_ALPHA, &w.rh, mi));
+    DP_TRY(blas(c, w, 0, n, OP_BICG_S, prec, mi, {&w.s, &w.r, &w.v}));
+    DP_TRY(schur(c, w, 0, n, prec, 0, w.s, w.to, w.t, mi, RED_TS4, FIN_BICG_OMEGA_RHO, &w.rh));
+    DP_TRY(blas(c, w, 0, n, OP_BICG_XRP, prec, mi, {&w.x, &w.p, &w.s, &w.r, &w.t, &w.v}, FIN_BICG_RR, mi));
+  } else if (b->solver == DP_SOLVER_BICGSTAB) {
     DP_TRY(blas(c, w, 0, n, OP_BICG_P, prec, mi, {&w.p, &w.r, &w.v}));
     DP_TRY(schur(c, w, 0, n, prec, 0, w.p, w.to, w.v, mi, RED_DOT_EXT, FIN_BICG_ALPHA, &w.rh, mi));
     DP_TRY(blas(c, w, 0, n, OP_BICG_S, prec, mi, {&w.s, &w.r, &w.v}));

@@ -36,9 +36,9 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
   if (a.mask && !a.mask[slot]) return;  // uniform over the slot's blocks
   const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const int Vh = g.Vh, Vp = g.Vp;
-  double red[4] = {0.0, 0.0, 0.0, 0.0};
+  double red[kRedMax] = {};
   int nv = 0;
-  if constexpr (OP == OP_BICG_INIT || OP == OP_CG_XR || OP == OP_SUB64 || OP == OP_NORM) nv = 1;
+  if constexpr (OP == OP_BICG_INIT || OP == OP_CG_XR || OP == OP_SUB64 || OP == OP_NORM || OP == OP_BICG_XRP) nv = 1;
   if constexpr (OP == OP_BICG_XR) nv = 3;
   if (i < Vh) {
     z A[12], B[12], C[12];
@@ -52,10 +52,10 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
     } else if constexpr (OP == OP_BICG_INIT) {
       ld<P>(a.v[1], slot, i, Vp, A);
       st<P>(a.v[0], slot, i, Vp, A);
+      st<P>(a.v[2], slot, i, Vp, A);
       red[0] = norm2(A);
 #pragma unroll
       for (int c = 0; c < 12; ++c) B[c] = z{0.0, 0.0};
-      st<P>(a.v[2], slot, i, Vp, B);
       st<P>(a.v[3], slot, i, Vp, B);
       st<PX>(a.v[4], slot, i, Vp, B);
     } else if constexpr (OP == OP_BICG_P) {
@@ -95,6 +95,25 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
       }
       red[2] = norm2(C);
       st<PX>(a.v[0], slot, i, Vp, A);
+      st<P>(a.v[3], slot, i, Vp, C);
+    } else if constexpr (OP == OP_BICG_XRP) {
+      const SlotScalars& s = a.sc[slot];
+      const z alpha{s.alpha[0], s.alpha[1]}, omega{s.omega[0], s.omega[1]}, beta{s.beta[0], s.beta[1]};
+      z D[12], E[12];
+      ld<PX>(a.v[0], slot, i, Vp, A);  // x
+      ld<P>(a.v[1], slot, i, Vp, B);   // p
+      ld<P>(a.v[2], slot, i, Vp, C);   // s
+      ld<P>(a.v[4], slot, i, Vp, D);   // t
+      ld<P>(a.v[5], slot, i, Vp, E);   // v
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        A[c] = A[c] + cmul(alpha, B[c]) + cmul(omega, C[c]);
+        C[c] = C[c] - cmul(omega, D[c]);                     // r
+        B[c] = C[c] + cmul(beta, B[c] - cmul(omega, E[c]));  // next p
+      }
+      red[0] = norm2(C);
+      st<PX>(a.v[0], slot, i, Vp, A);
+      st<P>(a.v[1], slot, i, Vp, B);
       st<P>(a.v[3], slot, i, Vp, C);
     } else if constexpr (OP == OP_CG_XR) {
       const double ca = a.sc[slot].cg_a;
@@ -153,11 +172,11 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
 __global__ void __launch_bounds__(kBlock) finalize_kernel(ReduceRef red, int nv, int nblocks, const int* mask) {
   const int slot = blockIdx.x;
   if (mask && !mask[slot]) return;
-  __shared__ double lds[4][kBlock / 64];
-  const double* part = red.partials + (long)slot * nblocks * 4;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  __shared__ double lds[kRedMax][kBlock / 64];
+  const double* part = red.partials + (long)slot * nblocks * kRedMax;
+  double acc[kRedMax] = {};
   for (int b = threadIdx.x; b < nblocks; b += kBlock)
-    for (int k = 0; k < nv; ++k) acc[k] += part[(long)b * 4 + k];
+    for (int k = 0; k < nv; ++k) acc[k] += part[(long)b * kRedMax + k];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int k = 0; k < nv; ++k) {
     const double w = wave_sum(acc[k]);
@@ -165,7 +184,7 @@ __global__ void __launch_bounds__(kBlock) finalize_kernel(ReduceRef red, int nv,
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    double s[kRedMax] = {};
     for (int k = 0; k < nv; ++k)
       for (int w = 0; w < kBlock / 64; ++w) s[k] += lds[k][w];
     run_finaliser(red, slot, s);
@@ -183,6 +202,7 @@ hipError_t launch_p(int op, const BlasArgs& a, dim3 grid, hipStream_t st) {
     DP_BLAS_CASE(OP_BICG_P)
     DP_BLAS_CASE(OP_BICG_S)
     DP_BLAS_CASE(OP_BICG_XR)
+    DP_BLAS_CASE(OP_BICG_XRP)
     DP_BLAS_CASE(OP_CG_XR)
     DP_BLAS_CASE(OP_CG_P)
     DP_BLAS_CASE(OP_SCALE_COPY)
@@ -199,7 +219,7 @@ hipError_t launch_p(int op, const BlasArgs& a, dim3 grid, hipStream_t st) {
 }  // namespace
 
 hipError_t launch_finalize(const ReduceRef& red, int nv, int nblocks, int nslots, const int* mask, hipStream_t st) {
-  if (nslots <= 0 || nv < 1 || nv > 4) return hipErrorInvalidValue;
+  if (nslots <= 0 || nv < 1 || nv > kRedMax) return hipErrorInvalidValue;
   hipLaunchKernelGGL(finalize_kernel, dim3(nslots), dim3(kBlock), 0, st, red, nv, nblocks, mask);
   return hipGetLastError();
 }
@@ -216,7 +236,9 @@ hipError_t launch_blas(int op, const BlasArgs& a, hipStream_t st) {
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess || a.red.fin == FIN_NONE) return e;
-  const int nv = op == OP_BICG_XR ? 3 : (op == OP_BICG_INIT || op == OP_CG_XR || op == OP_SUB64 || op == OP_NORM) ? 1 : 0;
+  const int nv = op == OP_BICG_XR ? 3
+                 : (op == OP_BICG_INIT || op == OP_CG_XR || op == OP_SUB64 || op == OP_NORM || op == OP_BICG_XRP) ? 1
+                                                                                                                   : 0;
   if (nv == 0) return hipErrorInvalidValue;
   return launch_finalize(a.red, nv, nb, a.nslots, a.mask, st);
 }

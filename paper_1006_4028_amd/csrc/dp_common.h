@@ -101,7 +101,14 @@ enum Red {
   RED_DOT_EXT = 1,  // <w, out>      (w = extra vector, e.g. the shadow residual)
   RED_TS = 2,       // <out, xin>, |out|^2
   RED_NORM = 3,     // |out|^2
+  RED_TS4 = 4,      // <out, xin>, |out|^2, <w, xin>, <w, out>
 };
+
+// values per reduction partial (at most 7 are used)
+constexpr int kRedMax = 8;
+__host__ __device__ constexpr int red_values(int red) {
+  return red == RED_DOT_EXT ? 2 : red == RED_TS ? 3 : red == RED_TS4 ? 7 : red == RED_NORM ? 1 : 0;
+}
 
 enum Fin {
   FIN_NONE = 0,
@@ -114,13 +121,15 @@ enum Fin {
   FIN_CG_INIT = 7,     // sums |z|^2              -> zz
   FIN_RR = 8,          // sums |r|^2              -> rr
   FIN_STORE = 9,       // raw sums                -> out_sums[slot][k]
+  FIN_BICG_OMEGA_RHO = 10,  // sums <t,s>, |t|^2, <rh,s>, <rh,t> -> omega, rho = <rh, s - omega t>, beta
+  FIN_BICG_RR = 11,         // sums |r|^2             -> rr, breakdown test, end of the iteration
 };
 
 struct ReduceRef {
   int red = RED_NONE;
   int fin = FIN_NONE;
   SpinorRef w;               // RED_DOT_EXT partner
-  double* partials = nullptr;   // [nslots][nblocks][4]
+  double* partials = nullptr;   // [nslots][nblocks][kRedMax]
   SlotScalars* sc = nullptr;    // [nslots]
   double* out_sums = nullptr;   // FIN_STORE: [nslots][4]
   int* inner_mask = nullptr;    // [nslots] cleared when a slot leaves the inner solve
@@ -210,7 +219,7 @@ struct BlasArgs {
 enum BlasOp {
   OP_ZERO = 0,        // v0 = 0
   OP_COPY = 1,        // v0 = v1                                  (P)
-  OP_BICG_INIT = 2,   // v0(rh) = v1(r); v2(p) = 0; v3(v) = 0; v4(x) = 0;  red |r|^2 -> FIN_BICG_INIT
+  OP_BICG_INIT = 2,   // v0(rh) = v1(r); v2(p) = r; v3(v) = 0; v4(x) = 0;  red |r|^2 -> FIN_BICG_INIT
   OP_BICG_P = 3,      // v0(p) = v1(r) + beta (p - omega v2(v))
   OP_BICG_S = 4,      // v0(s) = v1(r) - alpha v2(v)
   OP_BICG_XR = 5,     // v0(x) += alpha v1(p) + omega v2(s); v3(r) = s - omega v4(t); red <v5(rh), r>, |r|^2
@@ -221,6 +230,8 @@ enum BlasOp {
   OP_SUB64 = 10,      // v0(F64) = v1(F64) - v2(F64);             red |v0|^2
   OP_NORM = 11,       // red |v1|^2                               (precision of v1)
   OP_TO64 = 12,       // v0(F64) = v1(P)
+  OP_BICG_XRP = 13,   // v0(x) += alpha v1(p) + omega v2(s); v3(r) = s - omega v4(t);
+                      // p = r + beta (p - omega v5(v));  red |r|^2 -> FIN_BICG_RR
 };
 
 hipError_t launch_blas(int op, const BlasArgs& a, hipStream_t stream);

@@ -469,7 +469,7 @@ __device__ inline void end_of_iteration(const ReduceRef& red, int slot, SlotScal
 }
 
 // Solver finalisers: turn the folded sums of one slot into its scalars.
-__device__ inline void run_finaliser(const ReduceRef& red, int slot, const double (&s)[4]) {
+__device__ inline void run_finaliser(const ReduceRef& red, int slot, const double (&s)[kRedMax]) {
   if (red.fin == FIN_STORE) {
     for (int k = 0; k < 4; ++k) red.out_sums[slot * 4 + k] = s[k];
     return;
@@ -515,6 +515,42 @@ __device__ inline void run_finaliser(const ReduceRef& red, int slot, const doubl
       end_of_iteration(red, slot, c);
       break;
     }
+    case FIN_BICG_OMEGA_RHO: {
+      // omega = <t,s> / |t|^2, and the next rho = <rh, r> with r = s - omega t
+      // (r itself is formed afterwards, in the same kernel as the next search
+      // direction).  <rh, s> vanishes in exact arithmetic, but its measured
+      // value keeps rho tied to the stored vectors: without it the recurrence
+      // drifts and the FP32 solve stagnates (measured at 24^3x48).
+      if (s[2] > 0.0) {
+        c.omega[0] = s[0] / s[2];
+        c.omega[1] = s[1] / s[2];
+      } else {
+        c.omega[0] = c.omega[1] = 0.0;
+      }
+      double rn[2];
+      rn[0] = s[3] - (c.omega[0] * s[5] - c.omega[1] * s[6]);
+      rn[1] = s[4] - (c.omega[0] * s[6] + c.omega[1] * s[5]);
+      if (c.omega[0] == 0.0 && c.omega[1] == 0.0) c.breakdown = 3;
+      if (c.breakdown == 0 && (c.rho[0] != 0.0 || c.rho[1] != 0.0)) {
+        double q[2], w[2];
+        cdiv(rn, c.rho, q);         // rho_new / rho
+        cdiv(c.alpha, c.omega, w);  // alpha / omega
+        c.beta[0] = q[0] * w[0] - q[1] * w[1];
+        c.beta[1] = q[0] * w[1] + q[1] * w[0];
+      } else {
+        c.beta[0] = c.beta[1] = 0.0;
+      }
+      c.rho[0] = rn[0];
+      c.rho[1] = rn[1];
+      break;
+    }
+    case FIN_BICG_RR: {
+      c.rr = s[0];
+      const double mag = sqrt(c.rho[0] * c.rho[0] + c.rho[1] * c.rho[1]);
+      if (!(mag > 1e-14 * sqrt(c.rh2 * s[0]))) c.breakdown = 1;
+      end_of_iteration(red, slot, c);
+      break;
+    }
     case FIN_BICG_INIT: {
       c.rho[0] = s[0];
       c.rho[1] = 0.0;
@@ -553,9 +589,9 @@ __device__ inline void run_finaliser(const ReduceRef& red, int slot, const doubl
 // partials in block order (deterministic for a fixed launch shape; a slot's
 // result depends only on that slot's data).  Every thread of the block must
 // call this (no early return before it).
-__device__ inline void block_reduce_store(const ReduceRef& red, int nv, double (&v)[4], int slot, int block,
+__device__ inline void block_reduce_store(const ReduceRef& red, int nv, double (&v)[kRedMax], int slot, int block,
                                           int nblocks) {
-  __shared__ double lds[4][kBlock / 64];
+  __shared__ double lds[kRedMax][kBlock / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int k = 0; k < nv; ++k) {
     const double w = wave_sum(v[k]);
@@ -563,7 +599,7 @@ __device__ inline void block_reduce_store(const ReduceRef& red, int nv, double (
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double* part = red.partials + ((long)slot * nblocks + block) * 4;
+    double* part = red.partials + ((long)slot * nblocks + block) * kRedMax;
     const int nw = blockDim.x >> 6;  // blocks of 64 or kBlock threads
     for (int k = 0; k < nv; ++k) {
       double t = 0.0;

@@ -176,13 +176,13 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
 // values and scale, lc[73][64].
 template <int P, int EPI, int RED, bool NT, bool LDS>
 __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<typename Tr<P>::R> (&acc)[12],
-                                         double (&red)[4], const float* lc, int lane) {
+                                         double (&red)[kRedMax], const float* lc, int lane) {
   using R = typename Tr<P>::R;
   const Geom& g = a.g;
   cx<R> out[12], xin[12], wv[12];
   if constexpr (EPI == EPI_DIAG || EPI == EPI_SUB || EPI == EPI_INV_SUB)
     SpinorIO<P>::template load<NT>(a.xin, slot, i, g.Vp, xin);
-  if constexpr (RED == RED_DOT_EXT) SpinorIO<P>::template load<NT>(a.red.w, slot, i, g.Vp, wv);
+  // the dot partner w is loaded after the output is formed (fewer live registers)
   if constexpr (EPI == EPI_HOP) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) out[c] = R(-0.5) * acc[c];
@@ -221,6 +221,7 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
     herm_apply(B[1], R(0), &t[6], &out[6]);
   }
   SpinorIO<P>::template store<NT>(a.out, slot, i, g.Vp, out);
+  if constexpr (RED == RED_DOT_EXT || RED == RED_TS4) SpinorIO<P>::template load<NT>(a.red.w, slot, i, g.Vp, wv);
   if constexpr (RED == RED_DOT_EXT) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
@@ -233,6 +234,20 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
       red[0] += (double)out[c].x * (double)xin[c].x + (double)out[c].y * (double)xin[c].y;
       red[1] += (double)out[c].x * (double)xin[c].y - (double)out[c].y * (double)xin[c].x;
       red[2] += (double)out[c].x * (double)out[c].x + (double)out[c].y * (double)out[c].y;
+    }
+  } else if constexpr (RED == RED_TS4) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      red[0] += (double)out[c].x * (double)xin[c].x + (double)out[c].y * (double)xin[c].y;
+      red[1] += (double)out[c].x * (double)xin[c].y - (double)out[c].y * (double)xin[c].x;
+      red[2] += (double)out[c].x * (double)out[c].x + (double)out[c].y * (double)out[c].y;
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      red[3] += (double)wv[c].x * (double)xin[c].x + (double)wv[c].y * (double)xin[c].y;
+      red[4] += (double)wv[c].x * (double)xin[c].y - (double)wv[c].y * (double)xin[c].x;
+      red[5] += (double)wv[c].x * (double)out[c].x + (double)wv[c].y * (double)out[c].y;
+      red[6] += (double)wv[c].x * (double)out[c].y - (double)wv[c].y * (double)out[c].x;
     }
   } else if constexpr (RED == RED_NORM) {
 #pragma unroll
@@ -263,9 +278,11 @@ __device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool
     any = any || on[k];
   }
   if (!any) return;
-  double red[NS][4];
+  double red[NS][kRedMax];
 #pragma unroll
-  for (int k = 0; k < NS; ++k) red[k][0] = red[k][1] = red[k][2] = red[k][3] = 0.0;
+  for (int k = 0; k < NS; ++k)
+#pragma unroll
+    for (int q = 0; q < kRedMax; ++q) red[k][q] = 0.0;
   if (valid) {
     int x[4];
     eo_coords(g, a.p, i, x[0], x[1], x[2], x[3]);
@@ -302,13 +319,13 @@ __device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool
       if (on[k]) epilogue<P, EPI, RED, NT, LDS>(a, sl[k], i, acc[k], red[k], lc, lane);
   }
   if constexpr (RED != RED_NONE) {
-    constexpr int nv = RED == RED_DOT_EXT ? 2 : RED == RED_TS ? 3 : 1;
+    constexpr int nv = red_values(RED);
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       if (!on[k]) continue;
       if constexpr (LDS) {
         // the same sum as block_reduce_store over a 64-thread block
-        double* pt = a.red.partials + ((long)sl[k] * nparts + part) * 4;
+        double* pt = a.red.partials + ((long)sl[k] * nparts + part) * kRedMax;
         for (int q = 0; q < nv; ++q) {
           const double w = wave_sum(red[k][q]);
           if (lane == 0) pt[q] = 0.0 + w;
@@ -506,8 +523,14 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
     if constexpr (P == F32) {
       if (shared && nt && a.nslots >= 2 && !forced) {
         m.ngroups = a.nslots;
-        // waves per workgroup: the fewest passes of at most 8 waves
-        const int passes = (a.nslots + 7) / 8;
+        // waves per workgroup: the fewest passes of at most 8 waves (LDS
+        // holds two workgroups per CU, registers three waves per SIMD); the
+        // RED_TS4 kernel takes ~200 registers (two waves per SIMD) and runs
+        // 4-wave workgroups, measured on MI355X at 24^3x48 with 12 slots:
+        // 4 waves 3% faster per solve than 6.  Tuning knob: DP_HOP_TS4_WAVES.
+        static const int maxw_ts4 = std::min(8, std::max(1, env_knob("DP_HOP_TS4_WAVES", 4)));
+        const int maxw = RED == RED_TS4 ? maxw_ts4 : 8;
+        const int passes = (a.nslots + maxw - 1) / maxw;
         const dim3 sgrid(nparts), sblock(64 * ((a.nslots + passes - 1) / passes));
         hipLaunchKernelGGL((hop_kernel_shared<P, EPI, RED, 1, true, DAG>), sgrid, sblock,
                            shared_tile_bytes<P>(EPI == EPI_DIAG), st, a, m);
@@ -553,6 +576,7 @@ hipError_t launch_epi(const HopArgs& a, int ntiles, hipStream_t st, int* np) {
         case RED_DOT_EXT: return launch_ns<P, EPI_DIAG, RED_DOT_EXT, DAG>(a, ntiles, st, np);
         case RED_TS: return launch_ns<P, EPI_DIAG, RED_TS, DAG>(a, ntiles, st, np);
         case RED_NORM: return launch_ns<P, EPI_DIAG, RED_NORM, DAG>(a, ntiles, st, np);
+        case RED_TS4: return launch_ns<P, EPI_DIAG, RED_TS4, DAG>(a, ntiles, st, np);
         default: return hipErrorInvalidValue;
       }
     default: return hipErrorInvalidValue;

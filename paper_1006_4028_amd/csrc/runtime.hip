@@ -192,7 +192,7 @@ int ensure_ws(dp_ctx* c, Workspace& w, int nslots, int prec) {
   for (int k = 0; k < 3; ++k) DP_HIP(c, w.ainv_ptr[k].reserve(sizeof(void*) * n));
   DP_HIP(c, w.ainv_scale_ptr.reserve(sizeof(float*) * n));
   DP_HIP(c, w.sc.reserve(sizeof(SlotScalars) * n));
-  DP_HIP(c, w.partials.reserve(sizeof(double) * 4 * nb * n));
+  DP_HIP(c, w.partials.reserve(sizeof(double) * kRedMax * nb * n));
   DP_HIP(c, w.out_sums.reserve(sizeof(double) * 4 * n));
   DP_HIP(c, w.slot_scale.reserve(sizeof(double) * n));
   DP_HIP(c, w.x0src.reserve(sizeof(int) * n));
@@ -288,7 +288,7 @@ void hop_cost(dp_ctx* c, int prec, int epi, int red, int nact, double* bytes, do
     slot += 24 * b + sc;
     fl += 48;
   }
-  if (red == RED_DOT_EXT) {
+  if (red == RED_DOT_EXT || red == RED_TS4) {
     slot += 24 * b + sc;
     fl += 96;
   } else if (red != RED_NONE) {
@@ -375,7 +375,7 @@ int hop(dp_ctx* c, Workspace& w, int s0, int n, int prec, int p, int dag, int ep
     DP_TRY(timing_end(c, ev, name, bytes, flops));
   }
   if (red != RED_NONE) {
-    const int nv = red == RED_DOT_EXT ? 2 : red == RED_TS ? 3 : 1;
+    const int nv = red_values(red);
     DP_TRY(timing_begin(c, &ev));
     DP_HIP(c, launch_finalize(a.red, nv, nparts, n, a.slots.mask, c->stream));
     DP_TRY(timing_end(c, ev, "finalize", 0.0, 0.0));
