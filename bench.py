@@ -93,7 +93,7 @@ def pmc_summary(fetch_csv, write_csv, command):
 
     def is_hop(r):
         return "hop_kernel" in r["Kernel_Name"] and "<1, 2, 1," in r["Kernel_Name"] or \
-            "hop_kernel" in r["Kernel_Name"] and "<1, 2, 2," in r["Kernel_Name"]
+            "hop_kernel" in r["Kernel_Name"] and "<1, 2, 4," in r["Kernel_Name"]
 
     out = {}
     for key, path in (("fetch", fetch_csv), ("write", write_csv)):
@@ -106,7 +106,7 @@ def pmc_summary(fetch_csv, write_csv, command):
         out[key + "_scale"] = (1 << 20) / copy  # 1 GiB = 2^20 KiB moved by the copy
         out[key + "_launches"] = len(full)
     hbm = 1024 * (out["fetch_kib_per_launch"] * out["fetch_scale"] + out["write_kib_per_launch"] * out["write_scale"])
-    rec = {"kernel": "hop_f32_diag (hop_kernel_shared<1, 2, 1|2, 1>), 24^3x48, 12 slots", "command": command,
+    rec = {"kernel": "hop_f32_diag (hop_kernel_shared<1, 2, 1|4, 1>), 24^3x48, 12 slots", "command": command,
            "source_sha256": kernel_source_hash(), "hbm_bytes_per_launch": hbm, **out}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(rec, f, indent=1)
@@ -206,6 +206,10 @@ def main():
     name, st = max(hops.items(), key=lambda kv: kv[1]["ms"])
     avg_ms = st["ms"] / st["launches"]
     gbs = st["bytes"] / st["launches"] / (avg_ms * 1e-3) / 1e9
+    # a measured streaming rate of this library: s = r - alpha v (two vectors
+    # read, one written, no neighbours)
+    stream = stats.get(f"blas_{args.precision}_4")
+    stream_gbs = stream["bytes"] / (stream["ms"] * 1e-3) / 1e9 if stream and stream["ms"] > 0 else None
     all_hop_ms = sum(v["ms"] for v in hops.values())
     all_hop_gbs = sum(v["bytes"] for v in hops.values()) / (all_hop_ms * 1e-3) / 1e9
     log(f"  {solves_per_s:.1f} solves/s, p50 {pct(lat_ms, 0.5):.2f} ms, p99 {pct(lat_ms, 0.99):.2f} ms, "
@@ -302,7 +306,9 @@ def main():
                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "avg_launch_us": round(1e3 * avg_ms, 2),
                      "alg_bytes_per_launch": st["bytes"] / st["launches"],
-                     "all_hop_kernels_GBps": round(all_hop_gbs, 1)},
+                     "all_hop_kernels_GBps": round(all_hop_gbs, 1),
+                     "stream_GBps": round(stream_gbs, 1) if stream_gbs else None,
+                     "frac_of_stream": round(gbs / stream_gbs, 4) if stream_gbs else None},
         "cpu_baseline": cpu,
         "dslash": dslash,
         "serving": serving,

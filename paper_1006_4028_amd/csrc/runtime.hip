@@ -403,7 +403,8 @@ int blas(dp_ctx* c, Workspace& w, int s0, int n, int op, int prec, const int* ma
   DP_HIP(c, launch_blas(op, a, c->stream));
   if (c->timing) {
     // vectors read + written per site and slot
-    static const int nvec[] = {1, 2, 5, 4, 3, 7, 6, 3, 2, 3, 3, 1, 2};
+    static const int nvec[] = {1, 2, 5, 4, 3, 7, 6, 3, 2, 3, 3, 1, 2, 8};
+    static_assert(sizeof(nvec) / sizeof(nvec[0]) == OP_BICG_XRP + 1, "one entry per vector op");
     const double b = prec == F64 ? 8.0 : prec == F32 ? 4.0 : 2.0;
     const double bytes = (double)c->g.Vh * active_slots(c, mask, n) * nvec[op] * 24 * b;
     DP_TRY(timing_end(c, ev, std::string("blas_") + prec_name(prec) + "_" + std::to_string(op), bytes, 0.0));
