@@ -47,9 +47,13 @@ int upload_slot(dp_batch* b, int s) {
   const double m4 = 4.0 + sl.me->M;
   DP_TRY(h2d(c, w.m4.as<double>() + s, &m4, sizeof(double)));
   const void* p3[3] = {sl.me->a64.p, sl.me->a32.p, sl.me->a16.p};
-  for (int k = 0; k < 3; ++k) DP_TRY(h2d(c, static_cast<const void**>(w.ainv_ptr[k].p) + s, &p3[k], sizeof(void*)));
+  for (int k = 0; k < 3; ++k) {
+    DP_TRY(h2d(c, static_cast<const void**>(w.ainv_ptr[k].p) + s, &p3[k], sizeof(void*)));
+    w.h_ainv[k][s] = p3[k];
+  }
   const float* s16 = sl.me->s16.as<float>();
   DP_TRY(h2d(c, static_cast<const float**>(w.ainv_scale_ptr.p) + s, &s16, sizeof(float*)));
+  w.h_ainv_scale[s] = s16;
   DP_TRY(h2d(c, w.x0src.as<int>() + s, &sl.x0, sizeof(int)));
   return DP_OK;
 }
@@ -178,7 +182,10 @@ int inner_iterations(dp_batch* b, int k) {
     for (int j = 0; j < k; ++j) DP_TRY(inner_iteration(b));
     return DP_OK;
   }
-  if (!b->graph || b->graph_k != k) {
+  // the launches capture whether all slots share one mass (and its A_oo^-1)
+  const float* unused = nullptr;
+  const void* ainv = common_ainv(b->w, 0, b->nslots, b->prec, &unused);
+  if (!b->graph || b->graph_k != k || b->graph_ainv != ainv) {
     if (b->graph) {
       DP_HIP(c, hipGraphExecDestroy(b->graph));
       b->graph = nullptr;
@@ -197,6 +204,7 @@ int inner_iterations(dp_batch* b, int k) {
     (void)hipGraphDestroy(g);
     DP_HIP(c, e);
     b->graph_k = k;
+    b->graph_ainv = ainv;
   }
   DP_HIP(c, hipGraphLaunch(b->graph, c->stream));
   return DP_OK;

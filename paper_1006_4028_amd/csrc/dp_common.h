@@ -66,6 +66,10 @@ struct SlotTable {
   const int* mask = nullptr;      // [nslots] nonzero = slot takes part
   const void* const* ainv = nullptr;          // [nslots] A_oo^-1 field of the slot's mass
   const float* const* ainv_scale = nullptr;   // [nslots] FP16 scales (or null)
+  // the A_oo^-1 field when every slot of the launch has the same mass (the
+  // slots' own ainv entries then point to it too), else null
+  const void* ainv_common = nullptr;
+  const float* ainv_common_scale = nullptr;
 };
 
 // Solver scalars of one slot, device resident (written by the finalisers of

@@ -174,7 +174,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
 // own inputs and the output as streamed (read or written once per launch).
 // With LDS the clover blocks come from the workgroup's copy of the stored
 // values and scale, lc[73][64].
-template <int P, int EPI, int RED, bool NT, bool LDS>
+template <int P, int EPI, int RED, bool NT, bool LDS, bool LINV>
 __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<typename Tr<P>::R> (&acc)[12],
                                          double (&red)[kRedMax], const float* lc, int lane) {
   using R = typename Tr<P>::R;
@@ -215,8 +215,15 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
       for (int c = 0; c < 12; ++c) t[c] = R(-0.5) * acc[c];
     }
     HermBlock<R> B[2];
-    const float* sc = a.slots.ainv_scale ? a.slots.ainv_scale[slot] : nullptr;
-    CloverIO<P>::load(a.slots.ainv[slot], sc, i, g.Vp, B);
+    if constexpr (LDS && LINV) {  // every slot's A^-1 is the workgroup's copy
+      float r[72];
+#pragma unroll
+      for (int k = 0; k < 72; ++k) r[k] = lc[k * 64 + lane];
+      CloverIO<P>::assemble(r, lc[72 * 64 + lane], B);
+    } else {
+      const float* sc = a.slots.ainv_scale ? a.slots.ainv_scale[slot] : nullptr;
+      CloverIO<P>::load(a.slots.ainv[slot], sc, i, g.Vp, B);
+    }
     herm_apply(B[0], R(0), &t[0], &out[0]);
     herm_apply(B[1], R(0), &t[6], &out[6]);
   }
@@ -260,7 +267,7 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
 // (stored as the partial `part` of `nparts` per slot).
 // With LDS (one wave per slot group in a workgroup sharing links and clover)
 // each wave stores its own reduction partials.
-template <int P, int EPI, int RED, int NS, bool NT, bool DAG, bool LDS = false>
+template <int P, int EPI, int RED, int NS, bool NT, bool DAG, bool LDS = false, bool LINV = false>
 __device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool valid, int part, int nparts,
                                           const cx<typename Tr<P>::R>* lu = nullptr,
                                           const float* lc = nullptr, int lane = 0) {
@@ -316,7 +323,7 @@ __device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool
     hop_dir<P, 3, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
 #pragma unroll
     for (int k = 0; k < NS; ++k)
-      if (on[k]) epilogue<P, EPI, RED, NT, LDS>(a, sl[k], i, acc[k], red[k], lc, lane);
+      if (on[k]) epilogue<P, EPI, RED, NT, LDS, LINV>(a, sl[k], i, acc[k], red[k], lc, lane);
   }
   if constexpr (RED != RED_NONE) {
     constexpr int nv = red_values(RED);
@@ -406,7 +413,8 @@ constexpr size_t shared_tile_bytes(bool clover) {
 
 // At most 8 waves per workgroup (256 VGPRs per lane); each wave takes slot
 // groups wv, wv + nw, ...
-template <int P, int EPI, int RED, int NS, bool NT, bool DAG>
+// LINV: the odd-site epilogue's A^-1, the same for every slot, is staged too.
+template <int P, int EPI, int RED, int NS, bool NT, bool DAG, bool LINV>
 __global__ void __launch_bounds__(512) hop_kernel_shared(HopArgs a, SlabMap m) {
   using R = typename Tr<P>::R;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -423,14 +431,15 @@ __global__ void __launch_bounds__(512) hop_kernel_shared(HopArgs a, SlabMap m) {
   const bool valid = in_slab && sp < g.Vsh;
   const int i = valid ? x0 * g.Vsh + sp : 0;
   // fill: tasks 0..7 are the link directions (2 mu forward, 2 mu + 1 backward),
-  // task 8 the clover blocks; wave w takes tasks w, w + nw, ...
-  constexpr int ntask = EPI == EPI_DIAG ? 9 : 8;
+  // task 8 the clover blocks (even-site epilogue) or the A^-1 blocks all
+  // slots share (odd-site epilogues); wave w takes tasks w, w + nw, ...
+  constexpr bool blocks = EPI == EPI_DIAG || LINV;
   if (valid) {
     int x[4];
     eo_coords(g, a.p, i, x[0], x[1], x[2], x[3]);
 #pragma unroll
-    for (int t = 0; t < ntask; ++t) {
-      if (t % nw != wv) continue;
+    for (int t = 0; t < 9; ++t) {
+      if (t % nw != wv || (t == 8 && !blocks)) continue;
       if (t < 8) {
         const int mu = t >> 1;  // a constant once unrolled
         cx<R> u[9];
@@ -446,7 +455,8 @@ __global__ void __launch_bounds__(512) hop_kernel_shared(HopArgs a, SlabMap m) {
         for (int k = 0; k < 9; ++k) lu[(t * 9 + k) * 64 + lane] = u[k];
       } else {
         float r[72];
-        const float sc = CloverIO<P>::load_raw(a.clov.data, a.clov.scale, i, g.Vp, r);
+        const float sc = LINV ? CloverIO<P>::load_raw(a.slots.ainv_common, a.slots.ainv_common_scale, i, g.Vp, r)
+                              : CloverIO<P>::load_raw(a.clov.data, a.clov.scale, i, g.Vp, r);
 #pragma unroll
         for (int k = 0; k < 72; ++k) lc[k * 64 + lane] = r[k];
         lc[72 * 64 + lane] = sc;
@@ -459,8 +469,8 @@ __global__ void __launch_bounds__(512) hop_kernel_shared(HopArgs a, SlabMap m) {
     // keeps the compiler from hoisting the LDS reads out of this loop into
     // (many) registers
     asm volatile("" ::: "memory");
-    site_work<P, EPI, RED, NS, NT, DAG, true>(a, grp, i, valid, (xcd * g.T + x0) * m.maxc + cl, 8 * g.T * m.maxc, lu,
-                                              lc, lane);
+    site_work<P, EPI, RED, NS, NT, DAG, true, LINV>(a, grp, i, valid, (xcd * g.T + x0) * m.maxc + cl, 8 * g.T * m.maxc,
+                                                    lu, lc, lane);
   }
 }
 
@@ -532,8 +542,13 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
         const int maxw = RED == RED_TS4 ? maxw_ts4 : 8;
         const int passes = (a.nslots + maxw - 1) / maxw;
         const dim3 sgrid(nparts), sblock(64 * ((a.nslots + passes - 1) / passes));
-        hipLaunchKernelGGL((hop_kernel_shared<P, EPI, RED, 1, true, DAG>), sgrid, sblock,
-                           shared_tile_bytes<P>(EPI == EPI_DIAG), st, a, m);
+        constexpr bool inv = EPI == EPI_INV || EPI == EPI_INV_SUB;
+        if (inv && a.slots.ainv_common)
+          hipLaunchKernelGGL((hop_kernel_shared<P, EPI, RED, 1, true, DAG, inv>), sgrid, sblock,
+                             shared_tile_bytes<P>(true), st, a, m);
+        else
+          hipLaunchKernelGGL((hop_kernel_shared<P, EPI, RED, 1, true, DAG, false>), sgrid, sblock,
+                             shared_tile_bytes<P>(EPI == EPI_DIAG), st, a, m);
         *nparts_out = nparts;
         return hipGetLastError();
       }

@@ -100,6 +100,9 @@ struct Workspace {
   DevBuf ratio, m4, mask_inner, mask_outer, ainv_ptr[3], ainv_scale_ptr, sc, partials, out_sums, slot_scale, x0src,
       alpha, cpp;
   HostBuf h_sc, h_sums, h_mask, h_scale;
+  // host copy of the slots' A_oo^-1 fields per precision and FP16 scales
+  std::vector<const void*> h_ainv[3];
+  std::vector<const float*> h_ainv_scale;
   size_t device_bytes() const;
 };
 
@@ -184,6 +187,7 @@ struct dp_batch {
   // captured k-iteration graph
   hipGraphExec_t graph = nullptr;
   int graph_k = 0;
+  const void* graph_ainv = nullptr;  // the shared A_oo^-1 the graph's launches were captured with
   ~dp_batch();
 };
 
@@ -219,6 +223,9 @@ const double* space_ratios(dp_ctx* c, int variant);
 const double* space_profile(dp_ctx* c);     // nullptr without spatial profiles
 const double* space_hop_ratios(dp_ctx* c);  // nullptr without spatial profiles
 SlotTable slot_table(Workspace& w, int T, int s0, int prec, const int* mask);
+// the A_oo^-1 field (and FP16 scale) shared by the slots [s0, s0 + n) in
+// precision prec, or null when their masses differ
+const void* common_ainv(const Workspace& w, int s0, int n, int prec, const float** scale);
 
 // launch helpers over slots [s0, s0 + n) of a workspace
 int hop(dp_ctx* c, Workspace& w, int s0, int n, int prec, int p, int dag, int epi, double sign, const Field& in,

@@ -189,8 +189,12 @@ int ensure_ws(dp_ctx* c, Workspace& w, int nslots, int prec) {
   DP_HIP(c, w.m4.reserve(sizeof(double) * n));
   DP_HIP(c, w.mask_inner.reserve(sizeof(int) * n));
   DP_HIP(c, w.mask_outer.reserve(sizeof(int) * n));
-  for (int k = 0; k < 3; ++k) DP_HIP(c, w.ainv_ptr[k].reserve(sizeof(void*) * n));
+  for (int k = 0; k < 3; ++k) {
+    DP_HIP(c, w.ainv_ptr[k].reserve(sizeof(void*) * n));
+    w.h_ainv[k].assign(n, nullptr);
+  }
   DP_HIP(c, w.ainv_scale_ptr.reserve(sizeof(float*) * n));
+  w.h_ainv_scale.assign(n, nullptr);
   DP_HIP(c, w.sc.reserve(sizeof(SlotScalars) * n));
   DP_HIP(c, w.partials.reserve(sizeof(double) * kRedMax * nb * n));
   DP_HIP(c, w.out_sums.reserve(sizeof(double) * 4 * n));
@@ -323,6 +327,17 @@ SlotTable slot_table(Workspace& w, int T, int s0, int prec, const int* mask) {
   return t;
 }
 
+const void* common_ainv(const Workspace& w, int s0, int n, int prec, const float** scale) {
+  *scale = nullptr;
+  if (n <= 0 || s0 + n > (int)w.h_ainv[prec].size()) return nullptr;
+  const void* p0 = w.h_ainv[prec][s0];
+  const float* q0 = w.h_ainv_scale[s0];
+  for (int s = s0 + 1; s < s0 + n; ++s)
+    if (w.h_ainv[prec][s] != p0 || w.h_ainv_scale[s] != q0) return nullptr;
+  if (prec == F16) *scale = q0;
+  return p0;
+}
+
 int timing_harvest(dp_ctx* c) {
   for (auto& q : c->pending) {
     float ms = 0.f;
@@ -359,6 +374,7 @@ int hop(dp_ctx* c, Workspace& w, int s0, int n, int prec, int p, int dag, int ep
   a.clov.data = prec == F64 ? c->C64[p].p : prec == F32 ? c->C32[p].p : c->C16[p].p;
   a.clov.scale = prec == F16 ? c->C16s[p].as<float>() : nullptr;
   a.slots = slot_table(w, c->g.T, s0, prec, mask);
+  if (epi == EPI_INV || epi == EPI_INV_SUB) a.slots.ainv_common = common_ainv(w, s0, n, prec, &a.slots.ainv_common_scale);
   a.sratio = w.sratio;
   a.red = reduce_ref(w, s0, red, fin, inner_mask);
   if (wv) a.red.w = wv->ref(s0);
@@ -705,9 +721,11 @@ int apply_core(dp_ctx* c, const double2* in, double2* out, int n, int flags) {
     for (int k = 0; k < 3; ++k) {
       std::vector<const void*> v(n, p3[k]);
       DP_TRY(h2d(c, w.ainv_ptr[k].p, v.data(), sizeof(void*) * n));
+      std::copy(v.begin(), v.end(), w.h_ainv[k].begin());
     }
     std::vector<const float*> s16(n, me->s16.as<float>());
     DP_TRY(h2d(c, w.ainv_scale_ptr.p, s16.data(), sizeof(float*) * n));
+    std::copy(s16.begin(), s16.end(), w.h_ainv_scale.begin());
     c->apply_key = key;
   }
   const long col = 2L * g.Vh * 12;  // double2 per column
