@@ -85,6 +85,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // neighbour spinors and links that other sites of the sweep read again.
 
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef unsigned u4v __attribute__((ext_vector_type(4)));
 
@@ -111,6 +112,15 @@ __device__ __forceinline__ uint4 vld(const uint4* p) {
   if constexpr (NT) {
     const u4v v = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(p));
     return make_uint4(v.x, v.y, v.z, v.w);
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ float2 vld(const float2* p) {
+  if constexpr (NT) {
+    const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+    return make_float2(v.x, v.y);
   } else {
     return *p;
   }
@@ -296,12 +306,12 @@ struct LinkIO<F64> {
 };
 template <>
 struct LinkIO<F32> {
-  template <typename R>
+  template <typename R, bool NT = false>
   __device__ static __forceinline__ void load(const void* base, int mu, int i, int Vh, cx<R> (&u)[9]) {
     const float2* b = static_cast<const float2*>(base) + (long)mu * 9 * Vh;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const float2 v = b[(long)k * Vh + i];
+      const float2 v = vld<NT>(b + (long)k * Vh + i);
       u[k] = cx<R>{(R)v.x, (R)v.y};
     }
   }
@@ -361,11 +371,12 @@ struct CloverIO<F64> {
 // bitwise the same block and the same arithmetic after it.
 template <>
 struct CloverIO<F32> {
+  template <bool NT = false>
   __device__ static __forceinline__ float load_raw(const void* base, const float*, int i, int Vh, float (&r)[72]) {
     const float4* b = static_cast<const float4*>(base);
 #pragma unroll
     for (int k = 0; k < 18; ++k) {
-      const float4 v = b[(long)k * Vh + i];
+      const float4 v = vld<NT>(b + (long)k * Vh + i);
       r[4 * k] = v.x; r[4 * k + 1] = v.y; r[4 * k + 2] = v.z; r[4 * k + 3] = v.w;
     }
     return 1.f;

@@ -414,6 +414,7 @@ constexpr size_t shared_tile_bytes(bool clover) {
 // At most 8 waves per workgroup (256 VGPRs per lane); each wave takes slot
 // groups wv, wv + nw, ...
 // LINV: the odd-site epilogue's A^-1, the same for every slot, is staged too.
+constexpr bool kFillNT = true;
 template <int P, int EPI, int RED, int NS, bool NT, bool DAG, bool LINV>
 __global__ void __launch_bounds__(512) hop_kernel_shared(HopArgs a, SlabMap m) {
   using R = typename Tr<P>::R;
@@ -443,20 +444,23 @@ __global__ void __launch_bounds__(512) hop_kernel_shared(HopArgs a, SlabMap m) {
       if (t < 8) {
         const int mu = t >> 1;  // a constant once unrolled
         cx<R> u[9];
+        // links and blocks are read once per launch here: streamed past L2,
+        // which then keeps more of the neighbour spinors
         if ((t & 1) == 0) {
-          LinkIO<P>::load(a.U_out, mu, i, g.Vp, u);
+          LinkIO<P>::template load<R, kFillNT>(a.U_out, mu, i, g.Vp, u);
         } else {
           int y[4] = {x[0], x[1], x[2], x[3]};
           const int L = mu == 0 ? g.T : mu == 1 ? g.L1 : mu == 2 ? g.L2 : g.L3;
           y[mu] = x[mu] == 0 ? L - 1 : x[mu] - 1;
-          LinkIO<P>::load(a.U_in, mu, eo_index(g, y[0], y[1], y[2], y[3]), g.Vp, u);
+          LinkIO<P>::template load<R, kFillNT>(a.U_in, mu, eo_index(g, y[0], y[1], y[2], y[3]), g.Vp, u);
         }
 #pragma unroll
         for (int k = 0; k < 9; ++k) lu[(t * 9 + k) * 64 + lane] = u[k];
       } else {
         float r[72];
-        const float sc = LINV ? CloverIO<P>::load_raw(a.slots.ainv_common, a.slots.ainv_common_scale, i, g.Vp, r)
-                              : CloverIO<P>::load_raw(a.clov.data, a.clov.scale, i, g.Vp, r);
+        const float sc =
+            LINV ? CloverIO<P>::template load_raw<kFillNT>(a.slots.ainv_common, a.slots.ainv_common_scale, i, g.Vp, r)
+                 : CloverIO<P>::template load_raw<kFillNT>(a.clov.data, a.clov.scale, i, g.Vp, r);
 #pragma unroll
         for (int k = 0; k < 72; ++k) lc[k * 64 + lane] = r[k];
         lc[72 * 64 + lane] = sc;
