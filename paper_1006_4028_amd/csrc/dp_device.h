@@ -126,11 +126,6 @@ __device__ __forceinline__ float2 vld(const float2* p) {
   }
 }
 template <bool NT>
-__device__ __forceinline__ unsigned vld(const unsigned* p) {
-  if constexpr (NT) return __builtin_nontemporal_load(p);
-  else return *p;
-}
-template <bool NT>
 __device__ __forceinline__ float vld(const float* p) {
   if constexpr (NT) return __builtin_nontemporal_load(p);
   else return *p;
@@ -299,12 +294,12 @@ template <int P>
 struct LinkIO;
 template <>
 struct LinkIO<F64> {
-  template <typename R, bool NT = false>
+  template <typename R>
   __device__ static __forceinline__ void load(const void* base, int mu, int i, int Vh, cx<R> (&u)[9]) {
     const double2* b = static_cast<const double2*>(base) + (long)mu * 9 * Vh;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const double2 v = vld<NT>(b + (long)k * Vh + i);
+      const double2 v = b[(long)k * Vh + i];
       u[k] = cx<R>{(R)v.x, (R)v.y};
     }
   }
@@ -323,12 +318,12 @@ struct LinkIO<F32> {
 };
 template <>
 struct LinkIO<F16> {
-  template <typename R, bool NT = false>
+  template <typename R>
   __device__ static __forceinline__ void load(const void* base, int mu, int i, int Vh, cx<R> (&u)[9]) {
     const unsigned* b = static_cast<const unsigned*>(base) + (long)mu * 9 * Vh;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const float2 v = h2f(vld<NT>(b + (long)k * Vh + i));
+      const float2 v = h2f(b[(long)k * Vh + i]);
       u[k] = cx<R>{(R)v.x, (R)v.y};
     }
   }

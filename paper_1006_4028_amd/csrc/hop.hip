@@ -117,8 +117,7 @@ __device__ __forceinline__ void link_dag_mul(const cx<R> (&u)[9], const Half<R>&
 // loaded components (the projection and the link product are linear).
 // With LDS the links come from the workgroup's copy lu[8][9][64] (direction
 // 2 mu for the forward hop, 2 mu + 1 for the backward one; lane = site).
-// NTL streams the links past L2 (read once per launch with one slot).
-template <int P, int MU, int NS, bool DAG, bool LDS, bool NTL>
+template <int P, int MU, int NS, bool DAG, bool LDS>
 __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], const bool (&on)[NS], int i,
                                         const int (&x)[4],
                                         const typename Tr<P>::R (&cf)[NS], const typename Tr<P>::R (&cb)[NS],
@@ -140,7 +139,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
 #pragma unroll
     for (int k = 0; k < 9; ++k) u[k] = lu[((2 * MU) * 9 + k) * 64 + lane];
   } else {
-    LinkIO<P>::template load<R, NTL>(a.U_out, MU, i, g.Vp, u);
+    LinkIO<P>::load(a.U_out, MU, i, g.Vp, u);
   }
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
@@ -158,7 +157,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
 #pragma unroll
     for (int k = 0; k < 9; ++k) u[k] = lu[((2 * MU + 1) * 9 + k) * 64 + lane];
   } else {
-    LinkIO<P>::template load<R, NTL>(a.U_in, MU, jb, g.Vp, u);
+    LinkIO<P>::load(a.U_in, MU, jb, g.Vp, u);
   }
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
@@ -268,7 +267,7 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
 // (stored as the partial `part` of `nparts` per slot).
 // With LDS (one wave per slot group in a workgroup sharing links and clover)
 // each wave stores its own reduction partials.
-template <int P, int EPI, int RED, int NS, bool NT, bool DAG, bool LDS = false, bool LINV = false, bool NTL = false>
+template <int P, int EPI, int RED, int NS, bool NT, bool DAG, bool LDS = false, bool LINV = false>
 __device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool valid, int part, int nparts,
                                           const cx<typename Tr<P>::R>* lu = nullptr,
                                           const float* lc = nullptr, int lane = 0) {
@@ -318,10 +317,10 @@ __device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool
         off += 4 * Ls[k];
       }
     }
-    hop_dir<P, 0, NS, DAG, LDS, NTL>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
-    hop_dir<P, 1, NS, DAG, LDS, NTL>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
-    hop_dir<P, 2, NS, DAG, LDS, NTL>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
-    hop_dir<P, 3, NS, DAG, LDS, NTL>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
+    hop_dir<P, 0, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
+    hop_dir<P, 1, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
+    hop_dir<P, 2, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
+    hop_dir<P, 3, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
 #pragma unroll
     for (int k = 0; k < NS; ++k)
       if (on[k]) epilogue<P, EPI, RED, NT, LDS, LINV>(a, sl[k], i, acc[k], red[k], lc, lane);
@@ -371,7 +370,7 @@ __device__ __forceinline__ int slab_lo(int nch, int xcd) { return (nch * xcd) >>
 // No minimum-waves hint: measured on MI355X at 24^3x48 with 12 slots, asking
 // for 3 waves per SIMD in FP32 (two slots per thread) or 4 in FP16 makes the
 // compiler spill and the kernels slower.
-template <int P, int EPI, int RED, int NS, bool NT, bool DAG, bool NTL = false>
+template <int P, int EPI, int RED, int NS, bool NT, bool DAG>
 __global__ void __launch_bounds__(64) hop_kernel_slab(HopArgs a, SlabMap m) {
   const int xcd = blockIdx.x & 7;
   int j = blockIdx.x >> 3;
@@ -397,8 +396,7 @@ __global__ void __launch_bounds__(64) hop_kernel_slab(HopArgs a, SlabMap m) {
   const int sp = chunk * 64 + threadIdx.x;
   const bool valid = in_slab && sp < a.g.Vsh;
   const int i = valid ? x0 * a.g.Vsh + sp : 0;
-  site_work<P, EPI, RED, NS, NT, DAG, false, false, NTL>(a, grp, i, valid, (xcd * a.g.T + x0) * m.maxc + cl,
-                                                         8 * a.g.T * m.maxc);
+  site_work<P, EPI, RED, NS, NT, DAG>(a, grp, i, valid, (xcd * a.g.T + x0) * m.maxc + cl, 8 * a.g.T * m.maxc);
 }
 
 // Shared-tile mapping: the slab mapping's (XCD chunk, timeslice) with every
@@ -507,12 +505,6 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
   }();
   if (forced) ns = std::min(forced, a.nslots >= 2 ? 2 : 1);
   const int ngroups = (a.nslots + ns - 1) / ns;
-  // with one slot every link is read once: the odd-site kernels stream them
-  // past the caches (measured on MI355X at 24^3x48, FP32 and FP16: 13% faster;
-  // the even-site kernel, which follows, was 10% slower with streamed links
-  // and keeps them cached).  Tuning knob: DP_HOP_NTLINK = 0 turns it off.
-  constexpr bool odd_epi = EPI == EPI_INV || EPI == EPI_INV_SUB;
-  static const bool ntl = env_knob("DP_HOP_NTLINK", 1) == 1;
   // The mapping fixes how the fused reductions are partitioned, so it must not
   // depend on the number of slots: a slot's result is then bitwise the same
   // alone and in any batch.  Slabs (measured on MI355X at 24^3x48: 5% faster
@@ -561,13 +553,6 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
         else
           hipLaunchKernelGGL((hop_kernel_shared<P, EPI, RED, 1, true, DAG, false>), sgrid, sblock,
                              shared_tile_bytes<P>(EPI == EPI_DIAG), st, a, m);
-        *nparts_out = nparts;
-        return hipGetLastError();
-      }
-    }
-    if constexpr (odd_epi) {
-      if (nt && ntl && a.nslots == 1) {  // one slot, one slot per thread
-        hipLaunchKernelGGL((hop_kernel_slab<P, EPI, RED, 1, true, DAG, true>), grid, dim3(64), lds, st, a, m);
         *nparts_out = nparts;
         return hipGetLastError();
       }
