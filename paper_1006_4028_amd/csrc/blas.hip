@@ -168,14 +168,29 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
   if (nv > 0 && a.red.fin != FIN_NONE) block_reduce_store(a.red, nv, red, slot, blockIdx.x, gridDim.x);
 }
 
-// one block per slot: fold the block partials in block order, then finalise
-__global__ void __launch_bounds__(kBlock) finalize_kernel(ReduceRef red, int nv, int nblocks, const int* mask) {
+// one block per slot: fold the block partials in a fixed order, then
+// finalise.  The fold is latency bound (a few thousand partials per slot), so
+// the block is wide and each thread keeps four partials in flight.
+constexpr int kFinBlock = 1024;
+__global__ void __launch_bounds__(kFinBlock) finalize_kernel(ReduceRef red, int nv, int nblocks, const int* mask) {
   const int slot = blockIdx.x;
   if (mask && !mask[slot]) return;
-  __shared__ double lds[kRedMax][kBlock / 64];
+  __shared__ double lds[kRedMax][kFinBlock / 64];
   const double* part = red.partials + (long)slot * nblocks * kRedMax;
   double acc[kRedMax] = {};
-  for (int b = threadIdx.x; b < nblocks; b += kBlock)
+  int b = threadIdx.x;
+  for (; b + 3 * kFinBlock < nblocks; b += 4 * kFinBlock) {
+    double q[4][kRedMax];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < kRedMax; ++k) q[u][k] = k < nv ? part[(long)(b + u * kFinBlock) * kRedMax + k] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < kRedMax; ++k) acc[k] += q[u][k];
+  }
+  for (; b < nblocks; b += kFinBlock)
     for (int k = 0; k < nv; ++k) acc[k] += part[(long)b * kRedMax + k];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int k = 0; k < nv; ++k) {
@@ -186,7 +201,7 @@ __global__ void __launch_bounds__(kBlock) finalize_kernel(ReduceRef red, int nv,
   if (threadIdx.x == 0) {
     double s[kRedMax] = {};
     for (int k = 0; k < nv; ++k)
-      for (int w = 0; w < kBlock / 64; ++w) s[k] += lds[k][w];
+      for (int w = 0; w < kFinBlock / 64; ++w) s[k] += lds[k][w];
     run_finaliser(red, slot, s);
   }
 }
@@ -220,7 +235,7 @@ hipError_t launch_p(int op, const BlasArgs& a, dim3 grid, hipStream_t st) {
 
 hipError_t launch_finalize(const ReduceRef& red, int nv, int nblocks, int nslots, const int* mask, hipStream_t st) {
   if (nslots <= 0 || nv < 1 || nv > kRedMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(finalize_kernel, dim3(nslots), dim3(kBlock), 0, st, red, nv, nblocks, mask);
+  hipLaunchKernelGGL(finalize_kernel, dim3(nslots), dim3(kFinBlock), 0, st, red, nv, nblocks, mask);
   return hipGetLastError();
 }
 
