@@ -413,10 +413,14 @@ constexpr size_t shared_tile_bytes(bool clover) {
 
 // At most 8 waves per workgroup (256 VGPRs per lane); each wave takes slot
 // groups wv, wv + nw, ...
+// Workgroups of up to 12 waves (at most 168 registers per lane, three waves
+// per SIMD), 8 for the fused reduction with the shadow residual (~200).
+constexpr int shared_max_threads(int red) { return red == RED_TS4 ? 512 : 768; }
+
 // LINV: the odd-site epilogue's A^-1, the same for every slot, is staged too.
 constexpr bool kFillNT = true;
 template <int P, int EPI, int RED, int NS, bool NT, bool DAG, bool LINV>
-__global__ void __launch_bounds__(512) hop_kernel_shared(HopArgs a, SlabMap m) {
+__global__ void __launch_bounds__(shared_max_threads(RED)) hop_kernel_shared(HopArgs a, SlabMap m) {
   using R = typename Tr<P>::R;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<R>* lu = reinterpret_cast<cx<R>*>(smem);
@@ -537,13 +541,17 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
     if constexpr (P == F32) {
       if (shared && nt && a.nslots >= 2 && !forced) {
         m.ngroups = a.nslots;
-        // waves per workgroup: the fewest passes of at most 8 waves (LDS
-        // holds two workgroups per CU, registers three waves per SIMD); the
+        // waves per workgroup: the fewest passes of at most 12 waves, one
+        // 12-wave workgroup per CU (three waves per SIMD): half as many
+        // workgroups in flight per XCD as with two 6-wave ones, so the sweep
+        // front spans fewer timeslices and more of the x0 neighbours stay in
+        // L2 (measured on MI355X at 24^3x48 with 12 slots: 5% faster).  The
         // RED_TS4 kernel takes ~200 registers (two waves per SIMD) and runs
-        // 4-wave workgroups, measured on MI355X at 24^3x48 with 12 slots:
-        // 4 waves 3% faster per solve than 6.  Tuning knob: DP_HOP_TS4_WAVES.
+        // 4-wave workgroups (3% faster per solve than 6).  Tuning knobs:
+        // DP_HOP_MAXW, DP_HOP_TS4_WAVES.
         static const int maxw_ts4 = std::min(8, std::max(1, env_knob("DP_HOP_TS4_WAVES", 4)));
-        const int maxw = RED == RED_TS4 ? maxw_ts4 : 8;
+        static const int maxw_other = std::min(shared_max_threads(RED) / 64, std::max(1, env_knob("DP_HOP_MAXW", 12)));
+        const int maxw = RED == RED_TS4 ? maxw_ts4 : maxw_other;
         const int passes = (a.nslots + maxw - 1) / maxw;
         const dim3 sgrid(nparts), sblock(64 * ((a.nslots + passes - 1) / passes));
         constexpr bool inv = EPI == EPI_INV || EPI == EPI_INV_SUB;
