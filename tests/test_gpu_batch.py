@@ -119,3 +119,56 @@ def test_server_poisson_stream_and_memory_gate():
         srv.close()
     log("  gated:", s)
     assert s["rejected"] > 0 and s["done"] + s["rejected"] == 16
+
+
+def test_batch_mass_change_after_shared_inverse():
+    """A batch whose slots all hold one mass stages that mass's A_oo^-1 once
+    per workgroup (FP32 multi-slot kernels), and its captured iteration graph
+    bakes that in; requests of another mass admitted later must get their own
+    inverse (the graph is captured again).  Every column equals its solo
+    solve bit for bit."""
+    import torch
+    import paper_1006_4028_amd as dp
+    from paper_1006_4028_amd.serve import point_columns, profile
+    log("test_batch_mass_change_after_shared_inverse")
+    U = synth.gauge_su3(DIMS, 0.4, 23)
+    r = 1e-10
+    reqs = [dict(M=0.5, a0=0.4, x0=0, cols=4), dict(M=0.05, a0=0.1, x0=2, cols=2),
+            dict(M=0.5, a0=0.0, x0=5, cols=2)]
+    with lattice(DIMS) as L:
+        L.set_gauge(U)
+        L.set_clover(1.6)
+        got = {}
+        with dp.Batch(L, 4, "f32") as B:
+            def admit(k):
+                q = reqs[k]
+                eta = point_columns(DIMS, q["x0"], q["cols"])
+                S_t = torch.zeros(q["cols"], eta[0].size, dtype=torch.complex128, device="cuda")
+                slots = B.admit(torch.from_numpy(eta.reshape(q["cols"], -1)).cuda(), S_t, M=q["M"],
+                                alpha=profile(DIMS[0], q["a0"], q["x0"]), r=r, x0_src=q["x0"], tag=k)
+                q["S_t"] = S_t
+                return slots
+
+            def drain(until_free):
+                while B.status()["free"] < until_free:
+                    B.step(2)
+                    for res in B.harvest():
+                        got.setdefault(res["tag"], []).append(res)
+
+            assert admit(0) is not None  # every slot at M = 0.5: shared inverse
+            drain(4)
+            assert admit(1) is not None  # M = 0.05 next to stale M = 0.5 slots
+            assert admit(2) is not None  # and M = 0.5 again beside it
+            drain(4)
+        for k, q in enumerate(reqs):
+            assert len(got[k]) == q["cols"]
+            alpha = profile(DIMS[0], q["a0"], q["x0"])
+            S_b = q["S_t"].cpu().numpy().reshape((q["cols"],) + DIMS + (4, 3))
+            eta = point_columns(DIMS, q["x0"], q["cols"])
+            with lattice(DIMS) as L2:
+                L2.set_gauge(U)
+                L2.set_clover(1.6)
+                for c in range(q["cols"]):
+                    S1, _, _ = solo(L2, eta[c], q["M"], alpha, q["x0"], r, "f32")
+                    assert np.array_equal(S1, S_b[c]), (k, c)
+            log(f"  request {k}: iters {[res['info']['iters'] for res in got[k]]}")
