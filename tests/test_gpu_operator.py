@@ -130,24 +130,25 @@ def test_inner_precision_kernels(precision, tol):
                 assert e < tol
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32", "f16"])
-def test_apply_dev_multi_rhs_matches_per_column(precision):
+@pytest.mark.parametrize("precision,nrhs", [("f64", 5), ("f32", 5), ("f16", 5), ("f32", 13), ("f32", 2)])
+def test_apply_dev_multi_rhs_matches_per_column(precision, nrhs):
     """dp_apply_dev runs the multi-RHS kernels (every right-hand side a slot);
     each column must equal the one-slot dp_apply of that column bitwise (the
     slot arithmetic does not depend on the batch), for the full operator, the
     Schur operator and their adjoints; the per-launch timing samples match
-    the launch counts."""
+    the launch counts.  13 FP32 columns take two passes of the shared-tile
+    workgroup (7 waves, the last one idle in the second pass)."""
     import torch
     dims = (6, 4, 6, 4)
-    log(f"test_apply_dev_multi_rhs_matches_per_column {precision}")
+    log(f"test_apply_dev_multi_rhs_matches_per_column {precision} nrhs={nrhs}")
     U, _, alpha = setup_field(dims, 31)
-    psi = synth.random_spinor(dims, 8, nrhs=5)
+    psi = synth.random_spinor(dims, 8, nrhs=nrhs)
     with lattice(dims) as L:
         L.set_gauge(U)
         L.set_clover(1.6)
         L.set_mass(0.2)
         L.set_alpha(alpha)
-        in_t = torch.from_numpy(psi.reshape(5, -1)).cuda()
+        in_t = torch.from_numpy(psi.reshape(nrhs, -1)).cuda()
         out_t = torch.empty_like(in_t)
         for schur in (False, True):
             for dagger in (False, True):
@@ -158,7 +159,7 @@ def test_apply_dev_multi_rhs_matches_per_column(precision):
                     assert len(L.timing_samples(name)) == st["launches"]
                 L.set_timing(False)
                 got = out_t.cpu().numpy().reshape(psi.shape)
-                for k in range(5):
+                for k in range(nrhs):
                     ref = L.apply(psi[k], precond=True, dagger=dagger, schur=schur, precision=precision)
                     assert np.array_equal(got[k], ref), (schur, dagger, k)
         with pytest.raises(Exception):
