@@ -38,8 +38,8 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
   const int Vh = g.Vh, Vp = g.Vp;
   double red[kRedMax] = {};
   int nv = 0;
-  if constexpr (OP == OP_BICG_INIT || OP == OP_CG_XR || OP == OP_SUB64 || OP == OP_NORM || OP == OP_BICG_XRP) nv = 1;
-  if constexpr (OP == OP_BICG_XR) nv = 3;
+  if constexpr (OP == OP_CG_XR || OP == OP_SUB64 || OP == OP_NORM || OP == OP_BICG_XRP) nv = 1;
+  if constexpr (OP == OP_BICG_XR || OP == OP_BICG_INIT) nv = 3;
   if (i < Vh) {
     z A[12], B[12], C[12];
     if constexpr (OP == OP_ZERO) {
@@ -51,9 +51,22 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
       st<P>(a.v[0], slot, i, Vp, A);
     } else if constexpr (OP == OP_BICG_INIT) {
       ld<P>(a.v[1], slot, i, Vp, A);
-      st<P>(a.v[0], slot, i, Vp, A);
       st<P>(a.v[2], slot, i, Vp, A);
       red[0] = norm2(A);
+      // rho = <rh, r> with rh as stored (rounded when its precision is lower)
+      if constexpr (rh_prec(P) != P) {
+        static_assert(rh_prec(P) == F16, "a lower-precision rh is stored in FP16");
+        SpinorIO<F16>::store_decoded<false, true>(a.v[0], slot, i, Vp, A, B);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const z d = cjmul(B[c], A[c]);
+          red[1] += d.x;
+          red[2] += d.y;
+        }
+      } else {
+        st<P>(a.v[0], slot, i, Vp, A);
+        red[1] = red[0];
+      }
 #pragma unroll
       for (int c = 0; c < 12; ++c) B[c] = z{0.0, 0.0};
       st<P>(a.v[3], slot, i, Vp, B);
@@ -84,7 +97,7 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
       ld<P>(a.v[1], slot, i, Vp, B);   // p
       ld<P>(a.v[2], slot, i, Vp, C);   // s
       ld<P>(a.v[4], slot, i, Vp, D);   // t
-      ld<P>(a.v[5], slot, i, Vp, E);   // rh
+      ld<rh_prec(P)>(a.v[5], slot, i, Vp, E);  // rh
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         A[c] = A[c] + cmul(alpha, B[c]) + cmul(omega, C[c]);
@@ -251,9 +264,9 @@ hipError_t launch_blas(int op, const BlasArgs& a, hipStream_t st) {
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess || a.red.fin == FIN_NONE) return e;
-  const int nv = op == OP_BICG_XR ? 3
-                 : (op == OP_BICG_INIT || op == OP_CG_XR || op == OP_SUB64 || op == OP_NORM || op == OP_BICG_XRP) ? 1
-                                                                                                                   : 0;
+  const int nv = (op == OP_BICG_XR || op == OP_BICG_INIT)                                         ? 3
+                 : (op == OP_CG_XR || op == OP_SUB64 || op == OP_NORM || op == OP_BICG_XRP) ? 1
+                                                                                             : 0;
   if (nv == 0) return hipErrorInvalidValue;
   return launch_finalize(a.red, nv, nb, a.nslots, a.mask, st);
 }

@@ -108,6 +108,13 @@ enum Red {
   RED_TS4 = 4,      // <out, xin>, |out|^2, <w, xin>, <w, out>
 };
 
+// Storage precision of BiCGStab's shadow residual rh for inner precision P.
+// rh only enters dot products and may be any fixed vector not orthogonal to
+// the start residual: with an FP32 inner solver it is the start residual
+// rounded to FP16 (with per-site scales), which halves the bytes the two
+// even-site kernels of an iteration read for it.
+__host__ __device__ constexpr int rh_prec(int p) { return p == F32 ? F16 : p; }
+
 // values per reduction partial (at most 7 are used)
 constexpr int kRedMax = 8;
 __host__ __device__ constexpr int red_values(int red) {
@@ -119,7 +126,7 @@ enum Fin {
   FIN_BICG_ALPHA = 1,  // sums <rh, v>            -> alpha = rho / <rh, v>
   FIN_BICG_OMEGA = 2,  // sums <t, s>, |t|^2      -> omega
   FIN_BICG_RHO = 3,    // sums <rh, r>, |r|^2     -> rho, beta, rr, breakdown
-  FIN_BICG_INIT = 4,   // sums |r|^2 (rh = r)     -> rho, rr, rh2, alpha = omega = 1
+  FIN_BICG_INIT = 4,   // sums |r|^2, <rh, r>     -> rho, rr, rh2, alpha = omega = 1
   FIN_CG_ALPHA = 5,    // sums |w|^2              -> cg_a = zz / |w|^2
   FIN_CG_BETA = 6,     // sums |z|^2              -> cg_b = |z|^2 / zz, zz
   FIN_CG_INIT = 7,     // sums |z|^2              -> zz
@@ -223,7 +230,7 @@ struct BlasArgs {
 enum BlasOp {
   OP_ZERO = 0,        // v0 = 0
   OP_COPY = 1,        // v0 = v1                                  (P)
-  OP_BICG_INIT = 2,   // v0(rh) = v1(r); v2(p) = r; v3(v) = 0; v4(x) = 0;  red |r|^2 -> FIN_BICG_INIT
+  OP_BICG_INIT = 2,   // v0(rh) = v1(r); v2(p) = r; v3(v) = 0; v4(x) = 0;  red |r|^2, <rh, r> -> FIN_BICG_INIT
   OP_BICG_P = 3,      // v0(p) = v1(r) + beta (p - omega v2(v))
   OP_BICG_S = 4,      // v0(s) = v1(r) - alpha v2(v)
   OP_BICG_XR = 5,     // v0(x) += alpha v1(p) + omega v2(s); v3(r) = s - omega v4(t); red <v5(rh), r>, |r|^2

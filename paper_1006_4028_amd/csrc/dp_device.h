@@ -263,6 +263,13 @@ struct SpinorIO<F16> {
   }
   template <bool NT = false, typename R>
   __device__ static __forceinline__ void store(const SpinorRef& f, int slot, int i, int Vh, const cx<R> (&s)[12]) {
+    cx<R> unused[12];
+    store_decoded<NT, false>(f, slot, i, Vh, s, unused);
+  }
+  // store, and (DEC) return in q what load() will read back
+  template <bool NT, bool DEC, typename R>
+  __device__ static __forceinline__ void store_decoded(const SpinorRef& f, int slot, int i, int Vh,
+                                                       const cx<R> (&s)[12], cx<R> (&q)[12]) {
     uint4* b = static_cast<uint4*>(f.data) + (long)slot * f.slot_stride;
     float m = 0.f;
 #pragma unroll
@@ -284,6 +291,13 @@ struct SpinorIO<F16> {
       v.z = f2h((float)s[4 * k + 2].x * inv, (float)s[4 * k + 2].y * inv);
       v.w = f2h((float)s[4 * k + 3].x * inv, (float)s[4 * k + 3].y * inv);
       vst<NT>(b + (long)k * Vh + i, v);
+      if constexpr (DEC) {
+        const float2 a0 = h2f(v.x), a1 = h2f(v.y), a2 = h2f(v.z), a3 = h2f(v.w);
+        q[4 * k + 0] = cx<R>{(R)(a0.x * m), (R)(a0.y * m)};
+        q[4 * k + 1] = cx<R>{(R)(a1.x * m), (R)(a1.y * m)};
+        q[4 * k + 2] = cx<R>{(R)(a2.x * m), (R)(a2.y * m)};
+        q[4 * k + 3] = cx<R>{(R)(a3.x * m), (R)(a3.y * m)};
+      }
     }
   }
 };
@@ -563,8 +577,8 @@ __device__ inline void run_finaliser(const ReduceRef& red, int slot, const doubl
       break;
     }
     case FIN_BICG_INIT: {
-      c.rho[0] = s[0];
-      c.rho[1] = 0.0;
+      c.rho[0] = s[1];
+      c.rho[1] = s[2];
       c.rr = s[0];
       c.rh2 = s[0];
       c.alpha[0] = c.omega[0] = 1.0;

@@ -228,7 +228,8 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
     herm_apply(B[1], R(0), &t[6], &out[6]);
   }
   SpinorIO<P>::template store<NT>(a.out, slot, i, g.Vp, out);
-  if constexpr (RED == RED_DOT_EXT || RED == RED_TS4) SpinorIO<P>::template load<NT>(a.red.w, slot, i, g.Vp, wv);
+  if constexpr (RED == RED_DOT_EXT || RED == RED_TS4)
+    SpinorIO<rh_prec(P)>::template load<NT>(a.red.w, slot, i, g.Vp, wv);
   if constexpr (RED == RED_DOT_EXT) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
@@ -601,10 +602,16 @@ hipError_t launch_epi(const HopArgs& a, int ntiles, hipStream_t st, int* np) {
     case EPI_DIAG:
       switch (a.red.red) {
         case RED_NONE: return launch_ns<P, EPI_DIAG, RED_NONE, DAG>(a, ntiles, st, np);
-        case RED_DOT_EXT: return launch_ns<P, EPI_DIAG, RED_DOT_EXT, DAG>(a, ntiles, st, np);
+        // the reductions with the shadow residual belong to BiCGStab, which
+        // never applies the adjoint: those variants are not built
+        case RED_DOT_EXT:
+          if constexpr (DAG) return hipErrorInvalidValue;
+          else return launch_ns<P, EPI_DIAG, RED_DOT_EXT, DAG>(a, ntiles, st, np);
         case RED_TS: return launch_ns<P, EPI_DIAG, RED_TS, DAG>(a, ntiles, st, np);
         case RED_NORM: return launch_ns<P, EPI_DIAG, RED_NORM, DAG>(a, ntiles, st, np);
-        case RED_TS4: return launch_ns<P, EPI_DIAG, RED_TS4, DAG>(a, ntiles, st, np);
+        case RED_TS4:
+          if constexpr (DAG) return hipErrorInvalidValue;
+          else return launch_ns<P, EPI_DIAG, RED_TS4, DAG>(a, ntiles, st, np);
         default: return hipErrorInvalidValue;
       }
     default: return hipErrorInvalidValue;

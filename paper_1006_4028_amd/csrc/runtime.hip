@@ -181,8 +181,9 @@ int ensure_ws(dp_ctx* c, Workspace& w, int nslots, int prec) {
   const int px = prec == F16 ? F32 : prec;
   Field* f64s[] = {&w.eta_e, &w.eta_o, &w.b64, &w.x64, &w.r64, &w.t64, &w.to64};
   for (Field* f : f64s) DP_HIP(c, f->alloc(g, F64, n));
-  Field* fin[] = {&w.r, &w.rh, &w.p, &w.v, &w.s, &w.t, &w.to};
+  Field* fin[] = {&w.r, &w.p, &w.v, &w.s, &w.t, &w.to};
   for (Field* f : fin) DP_HIP(c, f->alloc(g, prec, n));
+  DP_HIP(c, w.rh.alloc(g, rh_prec(prec), n));
   DP_HIP(c, w.x.alloc(g, px, n));
   const int nb = std::max(reduction_blocks(g), hop_blocks(g));
   DP_HIP(c, w.ratio.reserve(sizeof(double) * 4 * g.T * n));
@@ -292,8 +293,9 @@ void hop_cost(dp_ctx* c, int prec, int epi, int red, int nact, double* bytes, do
     slot += 24 * b + sc;
     fl += 48;
   }
-  if (red == RED_DOT_EXT || red == RED_TS4) {
-    slot += 24 * b + sc;
+  if (red == RED_DOT_EXT || red == RED_TS4) {  // the shadow residual, stored in rh_prec(prec)
+    const int pw = rh_prec(prec);
+    slot += 24 * (pw == F64 ? 8.0 : pw == F32 ? 4.0 : 2.0) + (pw == F16 ? 4.0 : 0.0);
     fl += 96;
   } else if (red != RED_NONE) {
     fl += 96;
