@@ -145,7 +145,7 @@ def main():
     if args.sap_study:
         return sap_study()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md on sharding)",
+        print("bench.py measures one GPU: the library has no multi-GPU path (one process drives one GPU)",
               file=sys.stderr)
         sys.exit(2)
 
