@@ -432,7 +432,12 @@ __global__ void __launch_bounds__(shared_max_threads(RED)) hop_kernel_shared(Hop
   const Geom& g = a.g;
   const int xcd = blockIdx.x & 7;
   const int j = blockIdx.x >> 3;
-  const int cl = j % m.maxc, x0 = j / m.maxc;
+  // the even-site kernel sweeps the timeslices backwards: it reads the odd
+  // field the preceding odd-site kernel wrote in forward order, whose last
+  // timeslices are then still in the caches (measured on MI355X at 24^3x48
+  // with 12 slots: 3% faster).  The reduction partials are indexed by x0, so
+  // the sums do not depend on the order.
+  const int cl = j % m.maxc, x0 = EPI == EPI_DIAG ? g.T - 1 - j / m.maxc : j / m.maxc;
   const int chunk = slab_lo(m.nch, xcd) + cl;
   const bool in_slab = chunk < slab_lo(m.nch, xcd + 1);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
