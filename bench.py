@@ -12,6 +12,11 @@ timeslice C_PP agreement of the two, the dominant kernel's roofline (from
 HIP events on the library's stream) and the CPU oracle on one column are
 reported on the same line.
 
+The timed steps run the production path: each batch of inner iterations is
+replayed from a captured hipGraph and no launch is bracketed by events.  The
+per-kernel roofline comes from a separate pass of two steps with HIP events
+around every launch on the library's stream (graphs off).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
 import argparse
@@ -117,6 +122,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# C_PP of the 12 point-source columns from the FP64 oracle (written by
+# tests/golden/make_golden.py, which calls only oracle/)
+GOLDEN = {"su3_16c32": "tests/golden/cpp_su3_16c32_M0.5.txt", "su3_24c48": "tests/golden/cpp_su3_24c48_M0.5.txt"}
+
+
+def load_golden(workload):
+    import numpy as np
+    path = GOLDEN.get(workload)
+    if path is None or not os.path.exists(os.path.join(ROOT, path)):
+        return None
+    return np.loadtxt(os.path.join(ROOT, path))[:, 1]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,10 +144,14 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=40,
-                    help="requests in the served stream (0 skips the serving measurement)")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests in the served stream at the arrival rate (0 skips the serving measurement)")
+    ap.add_argument("--serve-capacity-requests", type=int, default=120,
+                    help="requests submitted at once to measure the capacity")
     ap.add_argument("--serve-rate", type=float, default=5.0,
                     help="Poisson arrival rate of the stream, 1/s (5/s is about 0.8 of the FP64-inner capacity)")
+    ap.add_argument("--serve-r", type=float, default=1e-11, help="residue of the served requests")
+    ap.add_argument("--roofline-steps", type=int, default=2, help="event-timed steps for the per-kernel roofline")
     ap.add_argument("--no-dslash", action="store_true", help="skip the operator (Dslash) benchmark")
     ap.add_argument("--dslash-calls", type=int, default=200, help="timed operator calls per case")
     ap.add_argument("--sap-study", action="store_true",
@@ -190,12 +212,18 @@ def main():
         L.set_timing(False)
         return total, lat, infos, cpp, stats
 
-    log(f"mixed path ({args.precision} inner): {args.warmup} warmup + {args.steps} timed steps")
-    total, lat, infos, cpp_mixed, stats = run(args.precision, args.steps, args.warmup, timing=True)
+    log(f"mixed path ({args.precision} inner): {args.warmup} warmup + {args.steps} timed steps (graph replay)")
+    total, lat, infos, cpp_mixed, _ = run(args.precision, args.steps, args.warmup)
     for i in infos:
         assert i["status"] == 0 and i["true_res"] <= r, i
     solves_per_s = ncols * args.steps / total
     lat_ms = sorted(1e3 * x for x in lat)
+    log(f"roofline pass: {args.roofline_steps} steps with HIP events around every launch (graphs off)")
+    t_ev, _, _, _, stats = run(args.precision, args.roofline_steps, 0, timing=True)
+    golden = load_golden(args.workload)
+
+    def vs_oracle(cpp):
+        return None if golden is None else float(np.abs(cpp / golden - 1).max())
 
     def pct(v, q):
         k = min(len(v) - 1, max(0, int(round(q * (len(v) - 1)))))
@@ -213,7 +241,9 @@ def main():
     all_hop_ms = sum(v["ms"] for v in hops.values())
     all_hop_gbs = sum(v["bytes"] for v in hops.values()) / (all_hop_ms * 1e-3) / 1e9
     log(f"  {solves_per_s:.1f} solves/s, p50 {pct(lat_ms, 0.5):.2f} ms, p99 {pct(lat_ms, 0.99):.2f} ms, "
-        f"iters {[i['iters'] for i in infos]}")
+        f"iters {[i['iters'] for i in infos]}; event-timed pass {1e3 * t_ev / args.roofline_steps:.1f} ms per step")
+    if golden is not None:
+        log(f"  C_PP vs the FP64 oracle (stored correlator), max per-timeslice rel err {vs_oracle(cpp_mixed[0]):.2e}")
     for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"]):
         log(f"  {k:18s} launches {v['launches']:6d} avg {1e3 * v['ms'] / v['launches']:8.1f} us "
             f"{v['bytes'] / (v['ms'] * 1e-3) / 1e9 if v['ms'] > 0 else 0:8.1f} GB/s")
@@ -229,7 +259,8 @@ def main():
         fp64 = {"value": round(ncols * args.steps / t64, 3), "unit": "solves/s",
                 "p50_ms": round(pct(lat64_ms, 0.5), 3), "p99_ms": round(pct(lat64_ms, 0.99), 3),
                 "iters": [i["iters"] for i in infos64],
-                "mixed_vs_fp64_cpp_max_rel_err_per_timeslice": cpp_err}
+                "mixed_vs_fp64_cpp_max_rel_err_per_timeslice": cpp_err,
+                "cpp_vs_oracle_max_rel_err_per_timeslice": vs_oracle(cpp64[0])}
         log(f"  {fp64['value']} solves/s; mixed/FP64 C_PP max rel err per timeslice {cpp_err:.2e}")
         if args.precision == "f32":
             # the lowest rung of the precision ladder, FP16 storage with per-site scales
@@ -242,7 +273,8 @@ def main():
                                  "p50_ms": round(pct(lat16_ms, 0.5), 3), "p99_ms": round(pct(lat16_ms, 0.99), 3),
                                  "iters": [i["iters"] for i in infos16],
                                  "vs_fp64_cpp_max_rel_err_per_timeslice":
-                                     float(np.abs(cpp16[0] / cpp64[0] - 1).max())}
+                                     float(np.abs(cpp16[0] / cpp64[0] - 1).max()),
+                                 "cpp_vs_oracle_max_rel_err_per_timeslice": vs_oracle(cpp16[0])}
             log(f"  {fp64['f16_inner']}")
 
     cpu = None
@@ -300,6 +332,9 @@ def main():
         "p50_ms": round(pct(lat_ms, 0.5), 3),
         "p99_ms": round(pct(lat_ms, 0.99), 3),
         "iters": [i["iters"] for i in infos],
+        "cpp_vs_oracle_max_rel_err_per_timeslice": vs_oracle(cpp_mixed[0]),
+        "cpp_oracle_reference": None if golden is None else GOLDEN[args.workload],
+        "event_timed_ms_per_step": round(1e3 * t_ev / args.roofline_steps, 3),
         "fp64": fp64,
         "speedup_vs_fp64": round(solves_per_s / fp64["value"], 3) if fp64 else None,
         "roofline": {"bound": "hbm", "kernel": name, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
@@ -436,10 +471,11 @@ def dslash_bench(args):
 def serve_stream(args, cfg3):
     """The served stream: resident 16^3x32 and 24^3x48 fields, each request
     drawing M from {0.01, 0.05, 0.2, 0.5}, alpha0 from {0, 0.1, 0.4} and 1-12
-    point-source columns at a random x0; batched solves to r = 1e-10 with the
-    FP32 inner solver and with the FP64 one.  Each is run twice: every request
-    arriving at once (the capacity, solves/s) and Poisson arrivals at the
-    given rate (latency, p50/p99)."""
+    point-source columns at a random x0; batched solves to the residue of the
+    metric (r = 1e-11 by default) with the FP32 inner solver and with the FP64
+    one.  Each is run twice: a stream of requests all arriving at once (the
+    capacity, solves/s) and Poisson arrivals at the given rate (latency,
+    p50/p99 over --serve-requests requests)."""
     import synth
     from paper_1006_4028_amd.serve import Server, poisson_requests, summarize
     cfg2 = synth.config("su3_16c32")
@@ -447,12 +483,13 @@ def serve_stream(args, cfg3):
               "24c48": (cfg3["dims"], synth.gauge_su3(cfg3["dims"], cfg3["eps"], cfg3["seed"]), cfg3["csw"])}
     T_of = {k: v[0][0] for k, v in fields.items()}
     out = {"workload": "16^3x32 + 24^3x48 resident, M in {0.01,0.05,0.2,0.5}, alpha0 in {0,0.1,0.4} "
-                       "(exp of min(t,T-t)), 1-12 columns at random x0, r=1e-10, 24 slots per field",
-           "rate_per_s": args.serve_rate, "requests": args.serve_requests}
+                       f"(exp of min(t,T-t)), 1-12 columns at random x0, r={args.serve_r}, 24 slots per field",
+           "r": args.serve_r, "rate_per_s": args.serve_rate, "requests": args.serve_requests,
+           "capacity_requests": args.serve_capacity_requests}
 
-    def run(prec, rate):
-        reqs = poisson_requests(args.serve_requests, rate, fields, T_of, seed=2024)
-        srv = Server(fields, nslots=24, precision=prec, r=1e-10, max_iter=20000, k=4)
+    def run(prec, rate, n):
+        reqs = poisson_requests(n, rate, fields, T_of, seed=2024)
+        srv = Server(fields, nslots=24, precision=prec, r=args.serve_r, max_iter=20000, k=4)
         try:
             s = summarize(srv, srv.run(reqs))
         finally:
@@ -461,15 +498,18 @@ def serve_stream(args, cfg3):
         return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in s.items()}
 
     for prec in ("f32", "f64"):
-        log(f"served stream, {prec} inner: {args.serve_requests} requests at once, then at {args.serve_rate}/s")
-        cap = run(prec, 1e6)
-        lat = run(prec, args.serve_rate)
-        out[prec] = {"capacity_solves_per_s": cap["solves_per_s"], "at_rate": lat}
+        log(f"served stream, {prec} inner, r={args.serve_r}: {args.serve_capacity_requests} requests at once, "
+            f"then {args.serve_requests} at {args.serve_rate}/s")
+        cap = run(prec, 1e6, args.serve_capacity_requests)
+        lat = run(prec, args.serve_rate, args.serve_requests)
+        out[prec] = {"capacity_solves_per_s": cap["solves_per_s"], "capacity_run": cap, "at_rate": lat}
     if out["f64"]["capacity_solves_per_s"] > 0:
         out["mixed_over_fp64_capacity"] = round(out["f32"]["capacity_solves_per_s"] /
                                                 out["f64"]["capacity_solves_per_s"], 3)
-    if out["f64"]["at_rate"]["p50_ms"] > 0:
+    if out["f32"]["at_rate"]["p50_ms"] > 0:
         out["fp64_over_mixed_p50_latency"] = round(out["f64"]["at_rate"]["p50_ms"] / out["f32"]["at_rate"]["p50_ms"], 3)
+    if out["f32"]["at_rate"]["p99_ms"] > 0:
+        out["fp64_over_mixed_p99_latency"] = round(out["f64"]["at_rate"]["p99_ms"] / out["f32"]["at_rate"]["p99_ms"], 3)
     return out
 
 

@@ -65,6 +65,10 @@ extern "C" {
 #define DP_PREC_F64 0 /* FP64 throughout */
 #define DP_PREC_F32 1 /* FP32 storage and arithmetic inside, FP64 outside */
 #define DP_PREC_F16 2 /* FP16 storage with per-site scales, FP32 arithmetic inside */
+#define DP_PREC_F32_SINGLE 3 /* one FP32 Krylov solve to r, no FP64 defect correction: the
+                                single-precision solve whose residue floor the heavy-quark
+                                section discusses (the FP64 residual is still recomputed
+                                once, for dp_info.true_res) */
 
 /* Krylov solver */
 #define DP_SOLVER_BICGSTAB 0 /* van der Vorst 1992 */
@@ -102,9 +106,14 @@ typedef struct {
   int restarts;      /* BiCGStab breakdown restarts */
   double true_res;   /* FP64 |eta' - D'S'| / |eta'| of the returned solution */
   double seconds;    /* wall time of the solve (shared by a batch) */
+  int fallback;      /* dp_solve*: 1 when the inner-precision solve of this column went
+                        non-finite and the returned result is the FP64 solve's */
 } dp_info;
 
-/* Create a context on GPU `device` for a lattice dims = {T, L1, L2, L3}
+/* Paper: eq. linsysunprec (the lattice on which D[U] + M acts) and, for the
+ * time boundary, eq. redeftbc (antiperiodic fermions) and the closing remark
+ * of the heavy-quark section (the Schroedinger functional's Dirichlet ends).
+ * Create a context on GPU `device` for a lattice dims = {T, L1, L2, L3}
  * (all even, >= 2), time boundary bc_t = -1 (antiperiodic), +1 (periodic) or
  * 0 (Dirichlet: the fermion vanishes beyond the first and last timeslice, the
  * boundary of the Schroedinger functional with zero boundary fields; the
@@ -114,24 +123,32 @@ int dp_create(const int dims[4], int bc_t, int device, dp_ctx** out);
 void dp_destroy(dp_ctx* ctx);
 const char* dp_last_error(const dp_ctx* ctx);
 
-/* Gauge links, host layout above (T*L1*L2*L3*4*9 complex).  Resets the clover
+/* Paper: the gauge field U of D[U] in eq. linsysunprec.
+ * Gauge links, host layout above (T*L1*L2*L3*4*9 complex).  Resets the clover
  * term to c_sw = 0 and drops cached per-mass inverses. */
 int dp_set_gauge(dp_ctx* ctx, const double* U);
 /* Same from device memory of the ctx's GPU. */
 int dp_set_gauge_dev(dp_ctx* ctx, const void* U_dev, void* hip_stream);
 
-/* Clover term c_sw (i/4) sum sigma F from the resident links (built on the GPU). */
+/* Paper: the O(a)-improved Wilson operator named at the start of the
+ * heavy-quark section, with the coefficient c_sw of the Table 1 caption.
+ * Clover term c_sw (i/4) sum sigma F from the resident links (built on the GPU). */
 int dp_set_clover(dp_ctx* ctx, double csw);
 /* A caller-supplied clover field, host layout [site][12][12]; it must be
  * Hermitian and commute with gamma5 (block diagonal in the two chiralities),
  * else DP_ERR_INVALID_ARG. */
 int dp_set_clover_field(dp_ctx* ctx, const double* C);
 
-/* Bare mass M (operator D + M), or kappa with M = 1/(2 kappa) - 4. */
+/* Paper: the quark mass M of eq. linsysunprec (the hopping parameters of
+ * Table 1 through M = 1/(2 kappa) - 4).
+ * Bare mass M (operator D + M), or kappa with M = 1/(2 kappa) - 4. */
 int dp_set_mass(dp_ctx* ctx, double M);
 int dp_set_kappa(dp_ctx* ctx, double kappa);
 
-/* Distance profile alpha(x0), T entries, each finite and > 0. */
+/* Paper: the function of eq. redeft (heavy-quark section), e.g. the profile
+ * of eq. pbcalpha; this table is its reciprocal (S' = alpha S).
+ * Distance profile alpha(x0), T entries, each finite and > 0.  Read at every
+ * later solve and dp_apply with DP_PRECOND; a copy is kept. */
 int dp_set_alpha(dp_ctx* ctx, const double* alpha);
 
 /* Spatial profiles of the light-quark factorisation (light-quark section,
@@ -145,7 +162,10 @@ int dp_set_alpha(dp_ctx* ctx, const double* alpha);
  * DP_ERR_BAD_STATE while a batch is open. */
 int dp_set_alpha_space(dp_ctx* ctx, const double* a1, const double* a2, const double* a3);
 
-/* out = op(in) for one full-lattice spinor (host layout).  flags:
+/* Paper: eq. linsysunprec (D + M) and eq. linsysprec (D' + M, the modified
+ * time derivatives of the heavy-quark section with the boundary rule eq.
+ * redeftbc).
+ * out = op(in) for one full-lattice spinor (host layout).  flags:
  * DP_PRECOND (alpha-preconditioned operator), DP_DAGGER (adjoint),
  * DP_HOP_ONLY (hopping term only) or DP_APPLY_SCHUR (even-odd Schur
  * operator), and DP_APPLY_F32 / DP_APPLY_F16 to run the inner-precision
@@ -153,7 +173,8 @@ int dp_set_alpha_space(dp_ctx* ctx, const double* a1, const double* a2, const do
  * operator uses the ctx's current gauge field, clover term, mass and alpha. */
 int dp_apply(dp_ctx* ctx, const double* in, double* out, int flags);
 
-/* dp_apply on nrhs spinors in device memory (host layout, nrhs consecutive
+/* Paper: as dp_apply (eqs. linsysunprec, linsysprec, redeftbc).
+ * dp_apply on nrhs spinors in device memory (host layout, nrhs consecutive
  * full-lattice spinors, complex128): the same flags and operator, each
  * right-hand side a slot of the multi-RHS kernels (the links are read once per
  * launch for all of them).  in and out must not overlap.  Work already queued
@@ -162,7 +183,10 @@ int dp_apply(dp_ctx* ctx, const double* in, double* out, int flags);
  * which makes this the operator benchmark. */
 int dp_apply_dev(dp_ctx* ctx, const void* in_dev, void* out_dev, int nrhs, int flags, void* hip_stream);
 
-/* Solve (D+M) S = eta for nrhs right-hand sides (host layout, nrhs spinors)
+/* Paper: eq. linsysunprec solved through eqs. redeft and linsysprec, stopped
+ * by eq. stopping (read as above), restored by eq. backcorrection (site by
+ * site, then contracted to C_PP of the heavy-quark section).
+ * Solve (D+M) S = eta for nrhs right-hand sides (host layout, nrhs spinors)
  * through the preconditioned system, to the residue p->r.
  *   S    : nullable; receives the nrhs restored solutions (host layout)
  *   cpp  : nullable; receives C_PP(t) = -sum_x tr[S^+ S], T doubles per group
@@ -172,11 +196,20 @@ int dp_apply_dev(dp_ctx* ctx, const void* in_dev, void* out_dev, int nrhs, int f
  * one hit max_iter (S, cpp and info are still filled), or another error. */
 int dp_solve(dp_ctx* ctx, const double* eta, int nrhs, const dp_params* p, double* S, double* cpp,
              dp_info* info);
-/* Same with eta and S in device memory (host layout); cpp and info on the host. */
+/* Paper: as dp_solve.
+ * Same with eta and S in device memory (host layout; they must not overlap,
+ * else DP_ERR_INVALID_ARG); cpp and info on the host.
+ * dp_solve and dp_solve_dev: a column whose FP32 / FP16 inner solve goes
+ * non-finite is solved again in FP64 (info.fallback = 1); a BiCGStab
+ * breakdown restarts the inner solve with a pseudo-random shadow residual,
+ * and three breakdowns in a row without progress end the column with
+ * DP_ERR_BREAKDOWN. */
 int dp_solve_dev(dp_ctx* ctx, const void* eta_dev, int nrhs, const dp_params* p, void* S_dev, double* cpp,
                  dp_info* info, void* hip_stream);
 
-/* SAP+GCR: the domain-decomposition solver of the paper's light-quark
+/* Paper: the solver of the light-quark iteration counts (Table 1 and the
+ * Schwarz-preconditioned GCR it cites), on the system of eqs. redefa, betaa.
+ * SAP+GCR: the domain-decomposition solver of the paper's light-quark
  * iteration counts (Table 1; the Schwarz alternating procedure it cites) on
  * the preconditioned system with the ctx's mass, time profile and spatial
  * profiles.  The lattice is cut into blocks of extents block[mu], each
@@ -196,7 +229,8 @@ typedef struct {
 /* One right-hand side (host layout); S and cpp (T doubles) nullable. */
 int dp_solve_sap(dp_ctx* ctx, const double* eta, const dp_sap_params* p, double* S, double* cpp, dp_info* info);
 
-/* Per-kernel timing of the library's own launches.  dp_set_timing(ctx, 1)
+/* Instrumentation (no passage of the paper: it reports no timings).
+ * Per-kernel timing of the library's own launches.  dp_set_timing(ctx, 1)
  * clears the statistics and brackets every later kernel launch of the ctx
  * with HIP events on the stream it runs on; dp_get_timing copies up to `max`
  * entries (one per kernel variant, e.g. "hop_f32_diag") and sets *count to
@@ -216,6 +250,30 @@ int dp_get_timing(dp_ctx* ctx, dp_kernel_stat* out, int max, int* count);
  * copied to ms, *count set to the number available (0 for an unknown name). */
 int dp_get_timing_samples(dp_ctx* ctx, const char* name, float* ms, int max, int* count);
 
+/* Paper: the point source of eq. linsysunprec (non-zero on one timeslice),
+ * placed as in the correlator C_PP of the heavy-quark section (all 12
+ * spin-colour components at one site).
+ * Writes ncols unit point sources into eta_dev (device memory of the ctx's
+ * GPU, ncols consecutive full-lattice spinors in host layout): column j is 1
+ * in spin-colour component c0 + j (c = 3*spin + colour) at site = {x0, x1,
+ * x2, x3} and 0 everywhere else.  Requires 0 <= c0, ncols >= 1, c0 + ncols
+ * <= 12 and the site inside the lattice, else DP_ERR_INVALID_ARG.  Work queued
+ * on hip_stream (nullable) completes first; returns when eta_dev is written.
+ * The caller owns eta_dev. */
+int dp_point_sources(dp_ctx* ctx, const int site[4], int c0, int ncols, void* eta_dev, void* hip_stream);
+
+/* Paper: as dp_apply (eqs. linsysunprec, linsysprec, redeftbc), with the
+ * mass of eq. linsysunprec and the profile of eq. redeft chosen per
+ * right-hand side, as the slots of a batch carry them.
+ * dp_apply_dev with a mass M[k] and a time profile alpha[k][0..T) for each
+ * right-hand side k (each slot of the multi-RHS kernels its own A_oo^-1 and
+ * hop ratios).  M NULL: the ctx's mass for every slot; alpha NULL: the ctx's
+ * profile (used with DP_PRECOND only).  Every M[k] finite and every alpha
+ * entry finite and > 0, else DP_ERR_INVALID_ARG.  A new mass allocates and
+ * caches its inverse clover field. */
+int dp_apply_dev_slots(dp_ctx* ctx, const void* in_dev, void* out_dev, int nrhs, int flags, const double* M,
+                       const double* alpha, void* hip_stream);
+
 /* ------------------------------------------------------------------ batches
  * A batch is a fixed set of nslots slots on one ctx, each solving one
  * right-hand side with its own mass, alpha profile, residue and source
@@ -234,6 +292,10 @@ typedef struct {
   dp_info info;    /* info.seconds = admission to completion */
 } dp_batch_result;
 
+/* Paper: each slot solves eq. linsysprec for its own eq. redeft profile,
+ * stopped by eq. stopping and restored by eq. backcorrection; the batching
+ * itself is no part of the paper.  precision DP_PREC_F64, _F32, _F16 or
+ * _F32_SINGLE, solver DP_SOLVER_*. */
 int dp_batch_open(dp_ctx* ctx, int nslots, int precision, int solver, dp_batch** out);
 void dp_batch_close(dp_batch* b);
 /* Admit ncols right-hand sides (device memory, host layout, one after the
@@ -254,7 +316,8 @@ int dp_batch_harvest(dp_batch* b, dp_batch_result* out, double* cpp, int max, in
 int dp_batch_status(const dp_batch* b, int* free_slots, int* running, int* done);
 long long dp_batch_device_bytes(const dp_batch* b);
 
-/* Device bytes a context would hold for the gauge field and clover of a
+/* Admission gate of a server (no passage of the paper).
+ * Device bytes a context would hold for the gauge field and clover of a
  * lattice, plus the solver work space for nrhs right-hand sides at the given
  * precision, plus one per-mass inverse per new mass. */
 long long dp_footprint_bytes(const int dims[4], int nrhs, int precision, int new_masses);

@@ -122,10 +122,12 @@ class Lattice:
         self._check(self._L.dp_apply(self._h, _ptr(psi), _ptr(out), flags))
         return out
 
-    def apply_dev(self, in_t, out_t, precond=False, dagger=False, hop_only=False, schur=False, precision="f64"):
+    def apply_dev(self, in_t, out_t, precond=False, dagger=False, hop_only=False, schur=False, precision="f64",
+                  masses=None, alphas=None):
         """dp_apply on torch CUDA tensors holding nrhs spinors in host layout
         (complex128, contiguous); every right-hand side is a slot of the
-        multi-RHS kernels."""
+        multi-RHS kernels.  masses (nrhs values) and alphas ([nrhs, T]) give
+        each slot its own mass and time profile (dp_apply_dev_slots)."""
         import torch
         assert in_t.is_cuda and out_t.is_cuda and in_t.is_contiguous() and out_t.is_contiguous()
         assert in_t.dtype == torch.complex128 and out_t.dtype == torch.complex128
@@ -135,8 +137,32 @@ class Lattice:
         flags |= (L.DP_HOP_ONLY if hop_only else 0) | (L.DP_APPLY_SCHUR if schur else 0)
         flags |= {"f64": 0, "f32": L.DP_APPLY_F32, "f16": L.DP_APPLY_F16}[precision]
         stream = torch.cuda.current_stream(in_t.device).cuda_stream
-        self._check(self._L.dp_apply_dev(self._h, ctypes.c_void_p(in_t.data_ptr()), ctypes.c_void_p(out_t.data_ptr()),
-                                         n, flags, ctypes.c_void_p(stream)))
+        if masses is None and alphas is None:
+            self._check(self._L.dp_apply_dev(self._h, ctypes.c_void_p(in_t.data_ptr()),
+                                             ctypes.c_void_p(out_t.data_ptr()), n, flags, ctypes.c_void_p(stream)))
+            return
+        m = None if masses is None else np.ascontiguousarray(masses, dtype=np.float64)
+        a = None if alphas is None else np.ascontiguousarray(alphas, dtype=np.float64)
+        assert m is None or m.shape == (n,)
+        assert a is None or a.shape == (n, self.T)
+        self._check(self._L.dp_apply_dev_slots(self._h, ctypes.c_void_p(in_t.data_ptr()),
+                                               ctypes.c_void_p(out_t.data_ptr()), n, flags,
+                                               _ptr(m) if m is not None else None, _ptr(a) if a is not None else None,
+                                               ctypes.c_void_p(stream)))
+
+    def point_sources(self, site, c0=0, ncols=12, out=None):
+        """Unit point sources at `site` in spin-colour components c0 .. c0+ncols-1,
+        written by dp_point_sources into a complex128 CUDA tensor [ncols, V*12]
+        (or into `out`)."""
+        import torch
+        if out is None:
+            out = torch.empty((ncols, self.V * 12), dtype=torch.complex128, device="cuda")
+        assert out.is_cuda and out.is_contiguous() and out.dtype == torch.complex128
+        assert out.numel() == ncols * self.V * 12
+        stream = torch.cuda.current_stream(out.device).cuda_stream
+        self._check(self._L.dp_point_sources(self._h, (ctypes.c_int * 4)(*[int(v) for v in site]), int(c0),
+                                             int(ncols), ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
+        return out
 
     # ------------------------------------------------------------ timing
     def set_timing(self, enable=True):
@@ -168,12 +194,15 @@ class Lattice:
     @staticmethod
     def _infos(info):
         return [dict(status=i.status, iters=i.iters, outer=i.outer, hop_calls=i.hop_calls,
-                     restarts=i.restarts, true_res=i.true_res, seconds=i.seconds) for i in info]
+                     restarts=i.restarts, true_res=i.true_res, seconds=i.seconds, fallback=i.fallback)
+                for i in info]
 
     def solve(self, eta, r=1e-11, solver="bicgstab", precision="f64", max_iter=10000, delta=0.0, x0_src=0,
-              ncols_group=0, want_S=True, allow_unconverged=False):
+              ncols_group=0, want_S=True, allow_unconverged=False, allow=()):
         """Solve (D+M) S = eta for eta of shape ([nrhs,] T, L1, L2, L3, 4, 3).
-        Returns (S, cpp, info)."""
+        precision: "f64", "f32", "f16" (inner precision under FP64 defect
+        correction) or "f32single" (one FP32 solve, no correction).
+        Returns (S, cpp, info); `allow` lists further return codes that do not raise."""
         eta = _c128(eta)
         if eta.ndim == 6:
             eta = eta[None]
@@ -185,7 +214,7 @@ class Lattice:
         p = self._params(r, solver, precision, max_iter, delta, x0_src, ncols_group)
         rc = self._L.dp_solve(self._h, _ptr(eta), n, ctypes.byref(p), _ptr(S) if want_S else None, _ptr(cpp),
                               info)
-        self._check(rc, allow=(L.DP_ERR_NOT_CONVERGED,) if allow_unconverged else ())
+        self._check(rc, allow=((L.DP_ERR_NOT_CONVERGED,) if allow_unconverged else ()) + tuple(allow))
         return S, cpp, self._infos(info)
 
     def solve_sap(self, eta, block, r=1e-10, ncy=5, nmr=4, nkv=16, precision="f32", max_iter=1000,
@@ -204,7 +233,7 @@ class Lattice:
         return S, cpp, self._infos([info])[0]
 
     def solve_dev(self, eta_t, S_t=None, r=1e-11, solver="bicgstab", precision="f64", max_iter=10000, delta=0.0,
-                  x0_src=0, ncols_group=0, allow_unconverged=False):
+                  x0_src=0, ncols_group=0, allow_unconverged=False, allow=()):
         """Device variant: eta_t (and S_t) are torch CUDA tensors in host layout."""
         import torch
         assert eta_t.is_cuda and eta_t.is_contiguous()
@@ -217,7 +246,7 @@ class Lattice:
         rc = self._L.dp_solve_dev(self._h, ctypes.c_void_p(eta_t.data_ptr()), n, ctypes.byref(p),
                                   ctypes.c_void_p(S_t.data_ptr()) if S_t is not None else None, _ptr(cpp), info,
                                   ctypes.c_void_p(stream))
-        self._check(rc, allow=(L.DP_ERR_NOT_CONVERGED,) if allow_unconverged else ())
+        self._check(rc, allow=((L.DP_ERR_NOT_CONVERGED,) if allow_unconverged else ()) + tuple(allow))
         return cpp, self._infos(info)
 
 
@@ -298,7 +327,8 @@ class Batch:
             i = o.info
             res.append(dict(tag=o.tag, slot=o.slot, cpp=cpp[k].copy(),
                             info=dict(status=i.status, iters=i.iters, outer=i.outer, hop_calls=i.hop_calls,
-                                      restarts=i.restarts, true_res=i.true_res, seconds=i.seconds)))
+                                      restarts=i.restarts, true_res=i.true_res, seconds=i.seconds,
+                                      fallback=i.fallback)))
         return res
 
     def release(self, tag):

@@ -20,7 +20,7 @@ DP_ERR_NONFINITE = -6
 DP_ERR_BAD_STATE = -7
 DP_ERR_FULL = -8
 
-DP_PREC = {"f64": 0, "f32": 1, "f16": 2}
+DP_PREC = {"f64": 0, "f32": 1, "f16": 2, "f32single": 3}
 DP_SOLVER = {"bicgstab": 0, "cgnr": 1}
 
 DP_PRECOND, DP_DAGGER, DP_HOP_ONLY = 1, 2, 4
@@ -30,7 +30,7 @@ DP_APPLY_SCHUR, DP_APPLY_F32, DP_APPLY_F16 = 8, 16, 32
 EXPORTED = [
     "dp_create", "dp_destroy", "dp_last_error", "dp_set_gauge", "dp_set_gauge_dev", "dp_set_clover",
     "dp_set_clover_field", "dp_set_mass", "dp_set_kappa", "dp_set_alpha", "dp_set_alpha_space", "dp_apply",
-    "dp_apply_dev", "dp_solve", "dp_solve_sap",
+    "dp_apply_dev", "dp_apply_dev_slots", "dp_point_sources", "dp_solve", "dp_solve_sap",
     "dp_solve_dev", "dp_footprint_bytes", "dp_set_timing", "dp_get_timing", "dp_get_timing_samples",
     "dp_batch_open", "dp_batch_close",
     "dp_batch_admit", "dp_batch_step", "dp_batch_harvest", "dp_batch_status", "dp_batch_device_bytes",
@@ -51,7 +51,7 @@ class dp_params(ctypes.Structure):
 class dp_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("outer", ctypes.c_int),
                 ("hop_calls", ctypes.c_int), ("restarts", ctypes.c_int), ("true_res", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("fallback", ctypes.c_int)]
 
 
 class dp_kernel_stat(ctypes.Structure):
@@ -105,6 +105,8 @@ def lib():
     L.dp_solve_sap.argtypes = [vp, dp, ctypes.POINTER(dp_sap_params), dp, dp, ctypes.POINTER(dp_info)]
     L.dp_apply.argtypes = [vp, dp, dp, ctypes.c_int]
     L.dp_apply_dev.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    L.dp_apply_dev_slots.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, dp, dp, vp]
+    L.dp_point_sources.argtypes = [vp, ip, ctypes.c_int, ctypes.c_int, vp, vp]
     L.dp_solve.argtypes = [vp, dp, ctypes.c_int, ctypes.POINTER(dp_params), dp, dp, ctypes.POINTER(dp_info)]
     L.dp_solve_dev.argtypes = [vp, vp, ctypes.c_int, ctypes.POINTER(dp_params), vp, dp,
                                ctypes.POINTER(dp_info), vp]

@@ -93,28 +93,44 @@ int outer_step(dp_batch* b, const std::vector<int>& pend, std::vector<int>& fini
     dp_batch::Slot& h = b->slots[s];
     h.outer++;
     h.hops += 2;
+    const double prev = h.res2;
     h.res2 = sums[4 * s];
+    // a breakdown that left the residual where it was counts towards giving up
+    if (h.has_inner && h.last_left == 2) h.stall = h.res2 < 0.99 * prev ? 0 : h.stall + 1;
+    else h.stall = 0;
     if (!std::isfinite(h.res2)) {
       h.status = DP_ERR_NONFINITE;
       finished.push_back(s);
     } else if (h.res2 <= h.r * h.r * h.eta2) {
       h.status = DP_OK;
       finished.push_back(s);
+    } else if (b->single && h.has_inner) {
+      // one inner solve only: its own stopping rule decides; true_res reports
+      // the FP64 residual of what it returned
+      h.status = h.last_left == 1 ? DP_OK
+                 : h.last_left == 2 ? DP_ERR_BREAKDOWN
+                 : h.last_left == 4 ? DP_ERR_NONFINITE
+                                    : DP_ERR_NOT_CONVERGED;
+      finished.push_back(s);
     } else if (h.iters >= h.max_iter) {
       h.status = DP_ERR_NOT_CONVERGED;
+      finished.push_back(s);
+    } else if (h.stall >= 3) {
+      h.status = DP_ERR_BREAKDOWN;
       finished.push_back(s);
     } else {
       start[s] = 1;
       any_start = true;
       h.scale = std::sqrt(h.res2);
-      const double need = 0.5 * h.r * std::sqrt(h.eta2 / h.res2);
-      double tol = prec == F64 ? need : std::max(need, h.delta);
+      const double need = (b->single ? 1.0 : 0.5) * h.r * std::sqrt(h.eta2 / h.res2);
+      double tol = prec == F64 || b->single ? need : std::max(need, h.delta);
       tol = std::min(tol, 0.5);
       SlotScalars& q = hsc[s];
       std::memset(&q, 0, sizeof q);
       q.tol2 = tol * tol;
       q.iters = h.iters;
       q.max_iter = h.max_iter;
+      q.shadow = h.has_inner && h.last_left == 2 ? 1 : 0;
       DP_HIP(c, hipMemcpyAsync(w.sc.as<SlotScalars>() + s, &q, sizeof q, hipMemcpyHostToDevice, c->stream));
     }
   }
@@ -257,16 +273,19 @@ int dp_batch_open(dp_ctx* c, int nslots, int precision, int solver, dp_batch** o
   if (!c || !out) return DP_ERR_INVALID_ARG;
   *out = nullptr;
   if (nslots <= 0 || nslots > 4096) return fail(c, DP_ERR_INVALID_ARG, "nslots must be in [1, 4096]");
-  if (precision < DP_PREC_F64 || precision > DP_PREC_F16) return fail(c, DP_ERR_INVALID_ARG, "unknown precision");
+  if (precision < DP_PREC_F64 || precision > DP_PREC_F32_SINGLE)
+    return fail(c, DP_ERR_INVALID_ARG, "unknown precision");
   if (solver != DP_SOLVER_BICGSTAB && solver != DP_SOLVER_CGNR) return fail(c, DP_ERR_INVALID_ARG, "unknown solver");
   DP_HIP(c, hipSetDevice(c->device));
   dp_batch* b = new (std::nothrow) dp_batch;
   if (!b) return fail(c, DP_ERR_OOM, "host allocation failed");
   b->c = c;
   b->nslots = nslots;
-  b->prec = precision;
+  b->api_prec = precision;
+  b->single = precision == DP_PREC_F32_SINGLE;
+  b->prec = b->single ? F32 : precision;
   b->solver = solver;
-  int rc = ensure_ws(c, b->w, nslots, precision);
+  int rc = ensure_ws(c, b->w, nslots, b->prec);
   b->w.sratio = space_hop_ratios(c);  // fixed while the batch is open
   if (rc != DP_OK) {
     delete b;
@@ -399,6 +418,7 @@ int dp_batch_step(dp_batch* b, int k, int* ndone) {
       h.iters = hsc[s].iters;
       if (!hm[s]) {
         if (hsc[s].left == 2) h.restarts++;
+        h.last_left = hsc[s].left;
         h.in_inner = false;
         b->m_inner[s] = 0;
         pend[s] = 1;
@@ -467,7 +487,8 @@ static int validate_params(dp_ctx* c, int nrhs, const dp_params* p) {
   if (!(p->r > 0) || !std::isfinite(p->r)) return fail(c, DP_ERR_INVALID_ARG, "r must be positive");
   if (p->solver != DP_SOLVER_BICGSTAB && p->solver != DP_SOLVER_CGNR)
     return fail(c, DP_ERR_INVALID_ARG, "unknown solver");
-  if (p->precision < DP_PREC_F64 || p->precision > DP_PREC_F16) return fail(c, DP_ERR_INVALID_ARG, "unknown precision");
+  if (p->precision < DP_PREC_F64 || p->precision > DP_PREC_F32_SINGLE)
+    return fail(c, DP_ERR_INVALID_ARG, "unknown precision");
   if (p->max_iter <= 0) return fail(c, DP_ERR_INVALID_ARG, "max_iter must be positive");
   if (p->delta < 0 || p->delta >= 1) return fail(c, DP_ERR_INVALID_ARG, "delta must be in [0, 1)");
   if (p->x0_src < 0 || p->x0_src >= c->g.T) return fail(c, DP_ERR_INVALID_ARG, "x0_src outside [0, T)");
@@ -484,20 +505,62 @@ static int solve_batch(dp_ctx* c, const double2* eta, int n, const dp_params& P,
 // the kept batch may hold slots that never finish, so it is dropped.
 static int solve_common(dp_ctx* c, const double2* eta, int n, const dp_params& P, double2* S, double* cpp_out,
                         dp_info* info) {
-  const int rc = solve_batch(c, eta, n, P, S, cpp_out, info);
-  if (rc != DP_OK && rc != DP_ERR_NOT_CONVERGED && rc != DP_ERR_NONFINITE && c->solve_batch) {
-    const std::string err = c->err;
-    dp_batch_close(c->solve_batch);
-    c->solve_batch = nullptr;
-    c->err = err;
+  const int T = c->g.T;
+  const int grp = P.ncols_group > 0 ? P.ncols_group : 1;
+  std::vector<dp_info> inf(n);
+  std::vector<double> per((size_t)n * T);
+  dp_params Pc = P;
+  Pc.ncols_group = 0;  // per column here; grouped below
+  int rc = solve_batch(c, eta, n, Pc, S, per.data(), inf.data());
+  if (rc != DP_OK && rc != DP_ERR_NOT_CONVERGED && rc != DP_ERR_NONFINITE && rc != DP_ERR_BREAKDOWN) {
+    if (c->solve_batch) {
+      const std::string err = c->err;
+      dp_batch_close(c->solve_batch);
+      c->solve_batch = nullptr;
+      c->err = err;
+    }
+    return rc;
   }
+  // A column whose FP32 / FP16 inner solve went non-finite is solved again in
+  // FP64, which the inner precision's range does not limit.
+  if (rc == DP_ERR_NONFINITE && P.precision != DP_PREC_F64) {
+    dp_params P64 = Pc;
+    P64.precision = DP_PREC_F64;
+    const size_t col = (size_t)2 * c->g.Vh * 12;  // double2 per column
+    for (int j = 0; j < n; ++j) {
+      if (inf[j].status != DP_ERR_NONFINITE) continue;
+      dp_info one{};
+      const int r1 = solve_batch(c, eta + j * col, 1, P64, S ? S + j * col : nullptr, per.data() + (size_t)j * T, &one);
+      if (r1 != DP_OK && r1 != DP_ERR_NOT_CONVERGED && r1 != DP_ERR_NONFINITE && r1 != DP_ERR_BREAKDOWN) return r1;
+      one.restarts += inf[j].restarts;
+      one.iters += inf[j].iters;
+      one.outer += inf[j].outer;
+      one.hop_calls += inf[j].hop_calls;
+      one.fallback = 1;
+      inf[j] = one;
+    }
+    rc = DP_OK;
+    for (int j = 0; j < n; ++j)
+      if (inf[j].status != DP_OK && rc == DP_OK) rc = inf[j].status;
+  }
+  if (info) std::copy(inf.begin(), inf.end(), info);
+  if (cpp_out)
+    for (int k = 0; k < n / grp; ++k)
+      for (int t = 0; t < T; ++t) {
+        double acc = 0.0;
+        for (int j = 0; j < grp; ++j) acc += per[(size_t)(k * grp + j) * T + t];
+        cpp_out[(size_t)k * T + t] = acc;
+      }
+  if (rc == DP_ERR_NOT_CONVERGED) c->err = "a right-hand side reached max_iter before the residue r";
+  if (rc == DP_ERR_NONFINITE) c->err = "a residual became NaN or Inf";
+  if (rc == DP_ERR_BREAKDOWN) c->err = "BiCGStab broke down three times in a row without progress";
   return rc;
 }
 
 static int solve_batch(dp_ctx* c, const double2* eta, int n, const dp_params& P, double2* S, double* cpp_out,
                        dp_info* info) {
   dp_batch*& b = c->solve_batch;
-  if (b && (b->nslots < n || b->prec != P.precision || b->solver != P.solver)) {
+  if (b && (b->nslots < n || b->api_prec != P.precision || b->solver != P.solver)) {
     dp_batch_close(b);
     b = nullptr;
   }
@@ -534,17 +597,7 @@ static int solve_batch(dp_ctx* c, const double2* eta, int n, const dp_params& P,
     }
     if (res[k].info.status != DP_OK && status == DP_OK) status = res[k].info.status;
   }
-  if (cpp_out) {
-    const int grp = P.ncols_group > 0 ? P.ncols_group : 1;
-    for (int k = 0; k < n / grp; ++k)
-      for (int t = 0; t < c->g.T; ++t) {
-        double acc = 0.0;
-        for (int j = 0; j < grp; ++j) acc += per[(size_t)(k * grp + j) * c->g.T + t];
-        cpp_out[(size_t)k * c->g.T + t] = acc;
-      }
-  }
-  if (status == DP_ERR_NOT_CONVERGED) c->err = "a right-hand side reached max_iter before the residue r";
-  if (status == DP_ERR_NONFINITE) c->err = "a residual became NaN or Inf";
+  if (cpp_out) std::copy(per.begin(), per.end(), cpp_out);  // per column (ncols_group is applied by the caller)
   return status;
 }
 
@@ -553,13 +606,14 @@ int dp_solve(dp_ctx* c, const double* eta, int nrhs, const dp_params* p, double*
   DP_HIP(c, hipSetDevice(c->device));
   DP_TRY(validate_params(c, nrhs, p));
   const size_t bytes = (size_t)nrhs * 2 * c->g.Vh * 12 * sizeof(double2);
-  DP_HIP(c, c->scratch_aos.reserve(bytes));
-  DP_HIP(c, hipMemcpyAsync(c->scratch_aos.p, eta, bytes, hipMemcpyHostToDevice, c->stream));
-  // S is written into the same buffer: every source is read at admission, before any S
-  int rc = solve_common(c, c->scratch_aos.as<double2>(), nrhs, *p, S ? c->scratch_aos.as<double2>() : nullptr, cpp,
-                        info);
-  if (S && (rc == DP_OK || rc == DP_ERR_NOT_CONVERGED)) {
-    DP_HIP(c, hipMemcpyAsync(S, c->scratch_aos.p, bytes, hipMemcpyDeviceToHost, c->stream));
+  // sources and solutions in separate halves (an FP64 retry reads a source again)
+  DP_HIP(c, c->scratch_aos.reserve(S ? 2 * bytes : bytes));
+  double2* deta = c->scratch_aos.as<double2>();
+  double2* dS = S ? deta + bytes / sizeof(double2) : nullptr;
+  DP_HIP(c, hipMemcpyAsync(deta, eta, bytes, hipMemcpyHostToDevice, c->stream));
+  int rc = solve_common(c, deta, nrhs, *p, dS, cpp, info);
+  if (S && (rc == DP_OK || rc == DP_ERR_NOT_CONVERGED || rc == DP_ERR_BREAKDOWN || rc == DP_ERR_NONFINITE)) {
+    DP_HIP(c, hipMemcpyAsync(S, dS, bytes, hipMemcpyDeviceToHost, c->stream));
     DP_HIP(c, hipStreamSynchronize(c->stream));
   }
   return rc;
@@ -570,6 +624,10 @@ int dp_solve_dev(dp_ctx* c, const void* eta, int nrhs, const dp_params* p, void*
   if (!c || !eta) return fail(c, DP_ERR_INVALID_ARG, "null argument");
   DP_HIP(c, hipSetDevice(c->device));
   DP_TRY(validate_params(c, nrhs, p));
+  const size_t bytes = (size_t)nrhs * 2 * c->g.Vh * 12 * sizeof(double2);
+  const char* e0 = static_cast<const char*>(eta);
+  const char* s0 = static_cast<const char*>(S);
+  if (S && e0 < s0 + bytes && s0 < e0 + bytes) return fail(c, DP_ERR_INVALID_ARG, "eta and S overlap");
   if (stream) DP_HIP(c, hipStreamSynchronize((hipStream_t)stream));
   return solve_common(c, static_cast<const double2*>(eta), nrhs, *p, static_cast<double2*>(S), cpp, info);
 }

@@ -24,6 +24,16 @@ __device__ __forceinline__ void st(const SpinorRef& f, int slot, int i, int Vh, 
   SpinorIO<P>::template store<true>(f, slot, i, Vh, s);
 }
 
+// Integer hash of Wellons' "lowbias32" (an xor-shift-multiply finaliser).
+__device__ __forceinline__ unsigned hash32(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
 __device__ __forceinline__ double norm2(const z (&a)[12]) {
   double s = 0.0;
 #pragma unroll
@@ -42,7 +52,8 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
   double red[kRedMax] = {};
   int nv = 0;
   if constexpr (OP == OP_CG_XR || OP == OP_SUB64 || OP == OP_NORM || OP == OP_BICG_XRP) nv = 1;
-  if constexpr (OP == OP_BICG_XR || OP == OP_BICG_INIT) nv = 3;
+  if constexpr (OP == OP_BICG_XR) nv = 3;
+  if constexpr (OP == OP_BICG_INIT) nv = 4;
   if (i < Vh) {
     z A[12], B[12], C[12];
     if constexpr (OP == OP_ZERO) {
@@ -56,19 +67,46 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
       ld<P>(a.v[1], slot, i, Vp, A);
       st<P>(a.v[2], slot, i, Vp, A);
       red[0] = norm2(A);
+      // The shadow residual rh only enters dot products: any fixed vector not
+      // orthogonal to r serves.  It is r itself, or, when the previous start
+      // broke down (<rh, M r> = 0), a pseudo-random vector of unit entries
+      // (+-1 +- i) drawn from an integer hash of (site, component), the same
+      // for every slot and every start.
+      const bool rnd = a.sc[slot].shadow != 0;  // uniform over the slot's blocks
+      if (rnd) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const unsigned h = hash32((unsigned)i * 12u + (unsigned)c);
+          C[c] = z{(h & 1u) ? 1.0 : -1.0, (h & 2u) ? 1.0 : -1.0};
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) C[c] = A[c];
+      }
       // rho = <rh, r> with rh as stored (rounded when its precision is lower)
       if constexpr (rh_prec(P) != P) {
         static_assert(rh_prec(P) == F16, "a lower-precision rh is stored in FP16");
-        SpinorIO<F16>::store_decoded<true, true>(a.v[0], slot, i, Vp, A, B);
+        SpinorIO<F16>::store_decoded<true, true>(a.v[0], slot, i, Vp, C, B);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
           const z d = cjmul(B[c], A[c]);
           red[1] += d.x;
           red[2] += d.y;
         }
+        red[3] = norm2(B);
+      } else if (rnd) {
+        st<P>(a.v[0], slot, i, Vp, C);  // unit entries: exact in every precision
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const z d = cjmul(C[c], A[c]);
+          red[1] += d.x;
+          red[2] += d.y;
+        }
+        red[3] = norm2(C);
       } else {
         st<P>(a.v[0], slot, i, Vp, A);
         red[1] = red[0];
+        red[3] = red[0];
       }
 #pragma unroll
       for (int c = 0; c < 12; ++c) B[c] = z{0.0, 0.0};
@@ -267,7 +305,8 @@ hipError_t launch_blas(int op, const BlasArgs& a, hipStream_t st) {
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess || a.red.fin == FIN_NONE) return e;
-  const int nv = (op == OP_BICG_XR || op == OP_BICG_INIT)                                         ? 3
+  const int nv = op == OP_BICG_INIT                                                              ? 4
+                 : op == OP_BICG_XR                                                           ? 3
                  : (op == OP_CG_XR || op == OP_SUB64 || op == OP_NORM || op == OP_BICG_XRP) ? 1
                                                                                              : 0;
   if (nv == 0) return hipErrorInvalidValue;

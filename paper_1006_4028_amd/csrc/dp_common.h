@@ -86,6 +86,8 @@ struct SlotScalars {
   int max_iter;   // ... or once iters reaches max_iter
   int breakdown;  // 1: rho collapsed, 2: <rh, v> = 0, 3: omega = 0
   int left;       // why it left: 1 converged, 2 breakdown, 3 max_iter, 4 non-finite
+  int shadow;     // BiCGStab shadow residual of the next start: 0 the start
+                  // residual, 1 a fixed pseudo-random vector (after a breakdown)
 };
 
 // Epilogues of the hop kernel.
@@ -126,7 +128,7 @@ enum Fin {
   FIN_BICG_ALPHA = 1,  // sums <rh, v>            -> alpha = rho / <rh, v>
   FIN_BICG_OMEGA = 2,  // sums <t, s>, |t|^2      -> omega
   FIN_BICG_RHO = 3,    // sums <rh, r>, |r|^2     -> rho, beta, rr, breakdown
-  FIN_BICG_INIT = 4,   // sums |r|^2, <rh, r>     -> rho, rr, rh2, alpha = omega = 1
+  FIN_BICG_INIT = 4,   // sums |r|^2, <rh, r>, |rh|^2 -> rho, rr, rh2, alpha = omega = 1
   FIN_CG_ALPHA = 5,    // sums |w|^2              -> cg_a = zz / |w|^2
   FIN_CG_BETA = 6,     // sums |z|^2              -> cg_b = |z|^2 / zz, zz
   FIN_CG_INIT = 7,     // sums |z|^2              -> zz
@@ -207,6 +209,10 @@ hipError_t launch_spinor_import(const Geom& g, const double2* aos, int nslots, l
 hipError_t launch_spinor_export(const Geom& g, SpinorRef even, SpinorRef odd, int nslots,
                                 const double* alpha_div, const double* sprof, double2* aos, long aos_slot_stride,
                                 hipStream_t stream);
+// ncols unit point sources (host layout, double2 per complex): column j is 1
+// in spin-colour component c0 + j at site {x0, x1, x2, x3}, 0 elsewhere.
+hipError_t launch_point_sources(const Geom& g, const int site[4], int c0, int ncols, double2* out,
+                                hipStream_t stream);
 // Per-timeslice sum of |psi|^2 over both parities, written to cpp[slot][t]
 // (as -sum, t = (x0 - x0_src[slot]) mod T), FP64 fields, divided by alpha^2.
 hipError_t launch_cpp(const Geom& g, SpinorRef even, SpinorRef odd, int nslots, const double* alpha,
@@ -230,7 +236,8 @@ struct BlasArgs {
 enum BlasOp {
   OP_ZERO = 0,        // v0 = 0
   OP_COPY = 1,        // v0 = v1                                  (P)
-  OP_BICG_INIT = 2,   // v0(rh) = v1(r); v2(p) = r; v3(v) = 0; v4(x) = 0;  red |r|^2, <rh, r> -> FIN_BICG_INIT
+  OP_BICG_INIT = 2,   // v0(rh) = v1(r) (or the pseudo-random shadow); v2(p) = r; v3(v) = 0; v4(x) = 0;
+                      // red |r|^2, <rh, r>, |rh|^2 -> FIN_BICG_INIT
   OP_BICG_P = 3,      // v0(p) = v1(r) + beta (p - omega v2(v))
   OP_BICG_S = 4,      // v0(s) = v1(r) - alpha v2(v)
   OP_BICG_XR = 5,     // v0(x) += alpha v1(p) + omega v2(s); v3(r) = s - omega v4(t); red <v5(rh), r>, |r|^2

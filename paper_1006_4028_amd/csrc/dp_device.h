@@ -131,6 +131,11 @@ __device__ __forceinline__ float vld(const float* p) {
   else return *p;
 }
 template <bool NT>
+__device__ __forceinline__ unsigned vld(const unsigned* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT>
 __device__ __forceinline__ void vst(float4* p, float4 v) {
   if constexpr (NT) {
     const f4v w = {v.x, v.y, v.z, v.w};
@@ -308,12 +313,12 @@ template <int P>
 struct LinkIO;
 template <>
 struct LinkIO<F64> {
-  template <typename R>
+  template <typename R, bool NT = false>
   __device__ static __forceinline__ void load(const void* base, int mu, int i, int Vh, cx<R> (&u)[9]) {
     const double2* b = static_cast<const double2*>(base) + (long)mu * 9 * Vh;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const double2 v = b[(long)k * Vh + i];
+      const double2 v = vld<NT>(b + (long)k * Vh + i);
       u[k] = cx<R>{(R)v.x, (R)v.y};
     }
   }
@@ -332,12 +337,12 @@ struct LinkIO<F32> {
 };
 template <>
 struct LinkIO<F16> {
-  template <typename R>
+  template <typename R, bool NT = false>
   __device__ static __forceinline__ void load(const void* base, int mu, int i, int Vh, cx<R> (&u)[9]) {
     const unsigned* b = static_cast<const unsigned*>(base) + (long)mu * 9 * Vh;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const float2 v = h2f(b[(long)k * Vh + i]);
+      const float2 v = h2f(vld<NT>(b + (long)k * Vh + i));
       u[k] = cx<R>{(R)v.x, (R)v.y};
     }
   }
@@ -415,17 +420,18 @@ struct CloverIO<F32> {
 };
 template <>
 struct CloverIO<F16> {
+  template <bool NT = false>
   __device__ static __forceinline__ float load_raw(const void* base, const float* scale, int i, int Vh,
                                                    float (&r)[72]) {
     const uint4* b = static_cast<const uint4*>(base);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const uint4 v = b[(long)k * Vh + i];
+      const uint4 v = vld<NT>(b + (long)k * Vh + i);
       float2 a0 = h2f(v.x), a1 = h2f(v.y), a2 = h2f(v.z), a3 = h2f(v.w);
       r[8 * k + 0] = a0.x; r[8 * k + 1] = a0.y; r[8 * k + 2] = a1.x; r[8 * k + 3] = a1.y;
       r[8 * k + 4] = a2.x; r[8 * k + 5] = a2.y; r[8 * k + 6] = a3.x; r[8 * k + 7] = a3.y;
     }
-    return scale[i];
+    return vld<NT>(scale + i);
   }
   template <typename R>
   __device__ static __forceinline__ void assemble(const float (&r)[72], float sc, HermBlock<R> (&B)[2]) {
@@ -506,6 +512,7 @@ __device__ inline void run_finaliser(const ReduceRef& red, int slot, const doubl
         c.breakdown = 2;
         c.alpha[0] = c.alpha[1] = 0.0;
         c.left = 2;
+        c.iters++;  // counted, so that max_iter bounds a run of breakdowns
         if (red.inner_mask) red.inner_mask[slot] = 0;
       } else {
         cdiv(c.rho, s, c.alpha);
@@ -580,7 +587,7 @@ __device__ inline void run_finaliser(const ReduceRef& red, int slot, const doubl
       c.rho[0] = s[1];
       c.rho[1] = s[2];
       c.rr = s[0];
-      c.rh2 = s[0];
+      c.rh2 = s[3];
       c.alpha[0] = c.omega[0] = 1.0;
       c.alpha[1] = c.omega[1] = 0.0;
       c.beta[0] = c.beta[1] = 0.0;

@@ -172,8 +172,9 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
 
 // Epilogue and fused reduction terms for one slot.  NT marks the epilogue's
 // own inputs and the output as streamed (read or written once per launch).
-// With LDS the clover blocks come from the workgroup's copy of the stored
-// values and scale, lc[73][64].
+// With LDS the clover blocks come from the workgroup's copy lc[72][64] of the
+// stored values times the FP16 per-site scale (the same product the direct
+// load forms, so the block is bitwise the same).
 template <int P, int EPI, int RED, bool NT, bool LDS, bool LINV>
 __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<typename Tr<P>::R> (&acc)[12],
                                          double (&red)[kRedMax], const float* lc, int lane) {
@@ -192,7 +193,7 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
       float r[72];
 #pragma unroll
       for (int k = 0; k < 72; ++k) r[k] = lc[k * 64 + lane];
-      CloverIO<P>::assemble(r, lc[72 * 64 + lane], B);
+      CloverIO<F32>::assemble(r, 1.f, B);  // the values are already scaled
     } else {
       CloverIO<P>::load(a.clov.data, a.clov.scale, i, g.Vp, B);
     }
@@ -215,11 +216,11 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
       for (int c = 0; c < 12; ++c) t[c] = R(-0.5) * acc[c];
     }
     HermBlock<R> B[2];
-    if constexpr (LDS && LINV) {  // every slot's A^-1 is the workgroup's copy
+    if constexpr (LDS && LINV) {  // every slot's A^-1 is the workgroup's copy (scaled)
       float r[72];
 #pragma unroll
       for (int k = 0; k < 72; ++k) r[k] = lc[k * 64 + lane];
-      CloverIO<P>::assemble(r, lc[72 * 64 + lane], B);
+      CloverIO<F32>::assemble(r, 1.f, B);
     } else {
       const float* sc = a.slots.ainv_scale ? a.slots.ainv_scale[slot] : nullptr;
       CloverIO<P>::load(a.slots.ainv[slot], sc, i, g.Vp, B);
@@ -413,13 +414,19 @@ __global__ void __launch_bounds__(64) hop_kernel_slab(HopArgs a, SlabMap m) {
 template <int P>
 constexpr size_t shared_tile_bytes(bool clover) {
   using R = typename Tr<P>::R;
-  return 8 * 9 * 64 * sizeof(cx<R>) + (clover ? 73 * 64 * sizeof(float) : 0);
+  return 8 * 9 * 64 * sizeof(cx<R>) + (clover ? 72 * 64 * sizeof(float) : 0);
 }
 
 // Workgroups of up to 12 waves (at most 168 registers per lane, three waves
 // per SIMD), 8 for the fused reduction with the shadow residual (~200); each
-// wave takes slot groups wv, wv + nw, ...
-constexpr int shared_max_threads(int red) { return red == RED_TS4 ? 512 : 768; }
+// wave takes slot groups wv, wv + nw, ...  FP16 storage needs more registers
+// for its neighbour loads (at three waves per SIMD the compiler spills): its
+// workgroups have 4 waves with two waves per SIMD (256 registers), two
+// workgroups per CU.
+template <int P>
+constexpr int shared_max_threads(int red) { return P == F16 ? 256 : red == RED_TS4 ? 512 : 768; }
+template <int P>
+constexpr int shared_min_waves() { return P == F16 ? 2 : 1; }
 
 // The staged links and blocks are read once per launch: streamed past L2
 // (measured on MI355X at 24^3x48 with 12 slots: 2-3% faster).
@@ -427,7 +434,8 @@ constexpr bool kFillNT = true;
 
 // LINV: the odd-site epilogue's A^-1, the same for every slot, is staged too.
 template <int P, int EPI, int RED, int NS, bool NT, bool DAG, bool LINV>
-__global__ void __launch_bounds__(shared_max_threads(RED)) hop_kernel_shared(HopArgs a, SlabMap m) {
+__global__ void __launch_bounds__(shared_max_threads<P>(RED), shared_min_waves<P>()) hop_kernel_shared(HopArgs a,
+                                                                                                   SlabMap m) {
   using R = typename Tr<P>::R;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<R>* lu = reinterpret_cast<cx<R>*>(smem);
@@ -476,8 +484,7 @@ __global__ void __launch_bounds__(shared_max_threads(RED)) hop_kernel_shared(Hop
             LINV ? CloverIO<P>::template load_raw<kFillNT>(a.slots.ainv_common, a.slots.ainv_common_scale, i, g.Vp, r)
                  : CloverIO<P>::template load_raw<kFillNT>(a.clov.data, a.clov.scale, i, g.Vp, r);
 #pragma unroll
-        for (int k = 0; k < 72; ++k) lc[k * 64 + lane] = r[k];
-        lc[72 * 64 + lane] = sc;
+        for (int k = 0; k < 72; ++k) lc[k * 64 + lane] = P == F16 ? r[k] * sc : r[k];
       }
     }
   }
@@ -548,8 +555,13 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
     // then takes 250 registers per lane).  Tuning knob: DP_HOP_SHARED = 0
     // keeps one workgroup per slot group.
     static const bool shared = env_knob("DP_HOP_SHARED", 1) == 1;
-    if constexpr (P == F32) {
-      if (shared && nt && a.nslots >= 2 && !forced) {
+    // FP16 storage through the shared-tile kernel: the links and the scaled
+    // clover values are converted to FP32 once in LDS, so the per-slot work is
+    // the FP32 kernel's plus the FP16 neighbour loads.  Tuning knob:
+    // DP_HOP_SHARED16 = 0 keeps the slab kernel for FP16.
+    static const bool shared16 = env_knob("DP_HOP_SHARED16", 1) == 1;
+    if constexpr (P == F32 || P == F16) {
+      if (shared && (P == F32 || shared16) && nt && a.nslots >= 2 && !forced) {
         m.ngroups = a.nslots;
         // waves per workgroup: the fewest passes of at most 12 waves, one
         // 12-wave workgroup per CU (three waves per SIMD): half as many
@@ -560,8 +572,9 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
         // 4-wave workgroups (3% faster per solve than 6).  Tuning knobs:
         // DP_HOP_MAXW, DP_HOP_TS4_WAVES.
         static const int maxw_ts4 = std::min(8, std::max(1, env_knob("DP_HOP_TS4_WAVES", 4)));
-        static const int maxw_other = std::min(shared_max_threads(RED) / 64, std::max(1, env_knob("DP_HOP_MAXW", 12)));
-        const int maxw = RED == RED_TS4 ? maxw_ts4 : maxw_other;
+        static const int maxw_other =
+            std::min(shared_max_threads<P>(RED) / 64, std::max(1, env_knob("DP_HOP_MAXW", 12)));
+        const int maxw = P == F16 ? shared_max_threads<P>(RED) / 64 : RED == RED_TS4 ? maxw_ts4 : maxw_other;
         const int passes = (a.nslots + maxw - 1) / maxw;
         const dim3 sgrid(nparts), sblock(64 * ((a.nslots + passes - 1) / passes));
         constexpr bool inv = EPI == EPI_INV || EPI == EPI_INV_SUB;

@@ -6,6 +6,8 @@
 // alpha(y0) a_1(y1) a_2(y2) a_3(y3): the time profile alpha of eq. redeft and
 // the spatial factors of the light-quark factorisation (eqs. redefa, betaa),
 // which must be divided out site by site before the contraction.
+#include <algorithm>
+
 #include "dp_device.h"
 
 namespace dp {
@@ -128,7 +130,29 @@ __global__ void __launch_bounds__(kBlock) cpp_kernel(Geom g, SpinorRef e, Spinor
   }
 }
 
+// Fill of ncols point-source columns (every entry written: no memset, so the
+// launch may sit in a captured graph).  Grid-stride over the 12 V ncols
+// complex entries.
+__global__ void __launch_bounds__(kBlock) point_source_kernel(long per_col, long at, int c0, int ncols,
+                                                              double2* __restrict__ out) {
+  const long total = per_col * ncols;
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
+    const long j = k / per_col, r = k - j * per_col;
+    out[k] = make_double2(r == at + c0 + j ? 1.0 : 0.0, 0.0);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_point_sources(const Geom& g, const int site[4], int c0, int ncols, double2* out, hipStream_t st) {
+  if (ncols <= 0 || c0 < 0 || c0 + ncols > 12) return hipErrorInvalidValue;
+  const long per_col = 2L * g.Vh * 12;
+  const long at = ((((long)site[0] * g.L1 + site[1]) * g.L2 + site[2]) * g.L3 + site[3]) * 12;
+  const long total = per_col * ncols;
+  const long blocks = std::min<long>((total + kBlock - 1) / kBlock, 8L * 1024);
+  hipLaunchKernelGGL(point_source_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, per_col, at, c0, ncols, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_gauge_reorder(const Geom& g, const double2* U_aos, void* U_eo[2], int prec, hipStream_t st) {
   const long V = 2L * g.Vh;

@@ -165,6 +165,8 @@ struct dp_ctx {
 struct dp_batch {
   dp_ctx* c = nullptr;
   int nslots = 0, prec = 0, solver = 0;
+  int api_prec = 0;     // the DP_PREC_* the batch was opened with
+  bool single = false;  // DP_PREC_F32_SINGLE: one inner solve, no FP64 defect correction
   dp::Workspace w;
   enum { FREE = 0, RUNNING = 1, DONE = 2 };
   struct Slot {
@@ -177,6 +179,8 @@ struct dp_batch {
     int max_iter = 0, x0 = 0;
     double eta2 = 0.0, res2 = 0.0, scale = 0.0;
     int iters = 0, outer = 0, restarts = 0, hops = 0, status = DP_OK;
+    int last_left = 0;  // why the last inner solve ended (SlotScalars::left)
+    int stall = 0;      // breakdowns in a row that left the FP64 residual where it was
     bool in_inner = false, has_inner = false;
     double t_admit = 0.0, t_done = 0.0;
     std::vector<double> cpp;

@@ -695,37 +695,50 @@ int check_apply_flags(dp_ctx* c, int flags) {
 }
 
 // The operator on n device spinors in host layout (in and out may not alias),
-// enqueued on the ctx stream.  The per-slot tables are uploaded only when the
-// mass, the alpha table, the precondition flag or the slot count changed.
-int apply_core(dp_ctx* c, const double2* in, double2* out, int n, int flags) {
+// enqueued on the ctx stream.  Slot k has the mass Ms[k] and the time profile
+// alphas[k * T ..] (null: the ctx's for every slot).  The per-slot tables are
+// uploaded only when the masses, the profiles, the precondition flag or the
+// slot count changed.
+int apply_core(dp_ctx* c, const double2* in, double2* out, int n, int flags, const double* Ms = nullptr,
+               const double* alphas = nullptr) {
   const int prec = (flags & DP_APPLY_F32) ? F32 : (flags & DP_APPLY_F16) ? F16 : F64;
   const int dag = (flags & DP_DAGGER) ? 1 : 0;
   Workspace& w = c->ws_apply;
   DP_TRY(ensure_ws(c, w, n, prec));
   w.sratio = (flags & DP_PRECOND) && c->has_space ? space_ratios(c, 1) : nullptr;
-  MassEntry* me = nullptr;
-  DP_TRY(mass_entry(c, c->M, &me));
   const Geom& g = c->g;
+  std::vector<MassEntry*> me(n, nullptr);
+  for (int k = 0; k < n; ++k) DP_TRY(mass_entry(c, Ms ? Ms[k] : c->M, &me[k]));
   std::vector<double> key;
   key.push_back((double)n);
-  key.push_back(c->M);
   key.push_back((flags & DP_PRECOND) ? 1.0 : 0.0);
-  for (const void* q : {me->a64.p, me->a32.p, me->a16.p, me->s16.p, w.ratio.p}) key.push_back((double)(uintptr_t)q);
-  if (flags & DP_PRECOND) key.insert(key.end(), c->alpha.begin(), c->alpha.end());
+  key.push_back((double)(uintptr_t)w.ratio.p);
+  for (int k = 0; k < n; ++k) {
+    key.push_back(me[k]->M);
+    key.push_back((double)(uintptr_t)me[k]);
+  }
+  if (flags & DP_PRECOND) {
+    if (alphas) key.insert(key.end(), alphas, alphas + (size_t)n * g.T);
+    else key.insert(key.end(), c->alpha.begin(), c->alpha.end());
+  }
   if (key != c->apply_key) {
-    std::vector<double> ones(g.T, 1.0), rt(4 * g.T), all((size_t)4 * g.T * n), m4(n, 4.0 + c->M), one(n, 1.0);
-    ratio_tables(g.T, c->bc_t, (flags & DP_PRECOND) ? c->alpha.data() : ones.data(), rt.data());
-    for (int k = 0; k < n; ++k) std::copy(rt.begin(), rt.end(), all.begin() + (size_t)4 * g.T * k);
+    std::vector<double> ones(g.T, 1.0), all((size_t)4 * g.T * n), m4(n), one(n, 1.0);
+    for (int k = 0; k < n; ++k) {
+      const double* a = !(flags & DP_PRECOND) ? ones.data() : alphas ? alphas + (size_t)k * g.T : c->alpha.data();
+      ratio_tables(g.T, c->bc_t, a, all.data() + (size_t)4 * g.T * k);
+      m4[k] = 4.0 + me[k]->M;
+    }
     DP_TRY(h2d(c, w.ratio.p, all.data(), sizeof(double) * all.size()));
     DP_TRY(h2d(c, w.m4.p, m4.data(), sizeof(double) * n));
     DP_TRY(h2d(c, w.slot_scale.p, one.data(), sizeof(double) * n));
-    const void* p3[3] = {me->a64.p, me->a32.p, me->a16.p};
-    for (int k = 0; k < 3; ++k) {
-      std::vector<const void*> v(n, p3[k]);
-      DP_TRY(h2d(c, w.ainv_ptr[k].p, v.data(), sizeof(void*) * n));
-      std::copy(v.begin(), v.end(), w.h_ainv[k].begin());
+    for (int q = 0; q < 3; ++q) {
+      std::vector<const void*> v(n);
+      for (int k = 0; k < n; ++k) v[k] = q == 0 ? me[k]->a64.p : q == 1 ? me[k]->a32.p : me[k]->a16.p;
+      DP_TRY(h2d(c, w.ainv_ptr[q].p, v.data(), sizeof(void*) * n));
+      std::copy(v.begin(), v.end(), w.h_ainv[q].begin());
     }
-    std::vector<const float*> s16(n, me->s16.as<float>());
+    std::vector<const float*> s16(n);
+    for (int k = 0; k < n; ++k) s16[k] = me[k]->s16.as<float>();
     DP_TRY(h2d(c, w.ainv_scale_ptr.p, s16.data(), sizeof(float*) * n));
     std::copy(s16.begin(), s16.end(), w.h_ainv_scale.begin());
     c->apply_key = key;
@@ -801,6 +814,44 @@ int dp_apply_dev(dp_ctx* c, const void* in, void* out, int nrhs, int flags, void
   DP_TRY(apply_core(c, static_cast<const double2*>(in), static_cast<double2*>(out), nrhs, flags));
   DP_HIP(c, hipStreamSynchronize(c->stream));
   DP_TRY(timing_harvest(c));
+  return DP_OK;
+}
+
+int dp_apply_dev_slots(dp_ctx* c, const void* in, void* out, int nrhs, int flags, const double* M,
+                       const double* alpha, void* stream) {
+  if (!c || !in || !out) return fail(c, DP_ERR_INVALID_ARG, "null argument");
+  if (nrhs <= 0) return fail(c, DP_ERR_INVALID_ARG, "nrhs must be positive");
+  DP_TRY(check_apply_flags(c, flags));
+  const Geom& g = c->g;
+  if (M)
+    for (int k = 0; k < nrhs; ++k)
+      if (!std::isfinite(M[k])) return fail(c, DP_ERR_INVALID_ARG, "masses must be finite");
+  if (alpha)
+    for (long k = 0; k < (long)nrhs * g.T; ++k)
+      if (!(alpha[k] > 0) || !std::isfinite(alpha[k]) || !std::isfinite(1.0 / alpha[k]))
+        return fail(c, DP_ERR_INVALID_ARG, "alpha must be finite and positive");
+  const size_t bytes = (size_t)nrhs * 2 * g.Vh * 12 * sizeof(double2);
+  const char* a = static_cast<const char*>(in);
+  const char* b = static_cast<const char*>(out);
+  if (a < b + bytes && b < a + bytes) return fail(c, DP_ERR_INVALID_ARG, "in and out overlap");
+  DP_HIP(c, hipSetDevice(c->device));
+  DP_TRY(check_state(c));
+  if (stream) DP_HIP(c, hipStreamSynchronize((hipStream_t)stream));
+  DP_TRY(apply_core(c, static_cast<const double2*>(in), static_cast<double2*>(out), nrhs, flags, M, alpha));
+  DP_HIP(c, hipStreamSynchronize(c->stream));
+  DP_TRY(timing_harvest(c));
+  return DP_OK;
+}
+
+int dp_point_sources(dp_ctx* c, const int site[4], int c0, int ncols, void* eta, void* stream) {
+  if (!c || !site || !eta) return fail(c, DP_ERR_INVALID_ARG, "null argument");
+  if (c0 < 0 || ncols < 1 || c0 + ncols > 12) return fail(c, DP_ERR_INVALID_ARG, "need 0 <= c0 and c0 + ncols <= 12");
+  for (int k = 0; k < 4; ++k)
+    if (site[k] < 0 || site[k] >= c->dims[k]) return fail(c, DP_ERR_INVALID_ARG, "site outside the lattice");
+  DP_HIP(c, hipSetDevice(c->device));
+  if (stream) DP_HIP(c, hipStreamSynchronize((hipStream_t)stream));
+  DP_HIP(c, launch_point_sources(c->g, site, c0, ncols, static_cast<double2*>(eta), c->stream));
+  DP_HIP(c, hipStreamSynchronize(c->stream));
   return DP_OK;
 }
 

@@ -510,6 +510,7 @@ extern "C" int dp_solve_sap(dp_ctx* c, const double* eta, const dp_sap_params* p
     o.outer = outer;
     o.hop_calls = 0;
     o.restarts = 0;
+    o.fallback = 0;
     o.true_res = e2.real() > 0 ? rn / std::sqrt(e2.real()) : 0.0;
     o.seconds = now_s() - t0;
   }

@@ -70,7 +70,6 @@ class FieldWorker(threading.Thread):
         self.occupancy = []
 
     def _try_admit(self, req):
-        import torch
         st = self.batch.status()
         if req.ncols > self.batch.nslots:
             req.status = "rejected_slots"
@@ -84,8 +83,7 @@ class FieldWorker(threading.Thread):
                     return True
                 self.mem["used"] += self.mass_bytes
             self.masses.add(req.M)
-        eta = point_columns(self.L.dims, req.x0, req.ncols)
-        eta_t = torch.from_numpy(eta.reshape(req.ncols, -1)).cuda()
+        eta_t = self.L.point_sources((req.x0, 0, 0, 0), 0, req.ncols)
         slots = self.batch.admit(eta_t, None, M=req.M, alpha=profile(self.L.T, req.alpha0, req.x0), r=self.r,
                                  max_iter=self.max_iter, x0_src=req.x0, tag=req.rid)
         assert slots is not None

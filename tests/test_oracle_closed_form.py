@@ -98,3 +98,38 @@ def test_spin_propagator_symmetry():
     lhs = np.conj(np.swapaxes(Ss, -1, -2))
     rhs = GAMMA5 @ neg @ GAMMA5
     np.testing.assert_allclose(lhs, rhs, atol=1e-14)
+
+
+@pytest.mark.parametrize("x0_src,profile", [(5, "exp"), (11, "exp"), (7, "cosh")])
+def test_source_timeslice_shift(x0_src, profile):
+    """A point source on timeslice x0_src of the free field.  Translation
+    invariance fixes the propagator: S(x) = s(x0) S_closed((x0 - x0_src) mod T,
+    x) with s = -1 for the sink timeslices the antiperiodic wrap separates
+    from the source (x0 < x0_src).  The correlator indexed by t = (x0 - x0_src)
+    mod T (the C_PP definition of the heavy-quark section, read for sources
+    off the origin as the distance from the source timeslice) must then equal
+    the closed form from the origin at every t.  The profile is measured from
+    the source timeslice, as the served requests use it."""
+    dims, M = (12, 4, 4, 4), 0.5
+    T = dims[0]
+    U = synth.free_gauge(dims)
+    a = synth.alpha_table(profile, T, 0.4, x0_src)
+    Sc = free_propagator_columns(dims, M)
+    sign = np.where(np.arange(T) < x0_src, -1.0, 1.0)[:, None, None, None, None, None]
+    S = []
+    for c in range(12):
+        eta = synth.point_source(dims, (x0_src, 0, 0, 0), c // 3, c % 3)
+        Sk, info = oracle.solve(U, None, M, eta, alpha=a, r=1e-13)
+        assert info["relres"] < 1e-12
+        ref = sign * np.roll(Sc[c], x0_src, axis=0)
+        np.testing.assert_allclose(Sk, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+        S.append(Sk)
+    S = np.stack(S)
+    c_cf = free_cpp(dims, M)
+    np.testing.assert_allclose(oracle.cpp(S, x0_src=x0_src), c_cf, rtol=1e-11)
+    # the unshifted index puts the source's correlator at its lattice timeslice
+    np.testing.assert_allclose(oracle.cpp(S, x0_src=0)[x0_src], c_cf[0], rtol=1e-11)
+    # a subset of columns: C_PP sums over the given columns only
+    np.testing.assert_allclose(oracle.cpp(S[:3], x0_src=x0_src),
+                               -np.sum(np.abs(np.roll(Sc[:3], 0, axis=1)) ** 2, axis=(0, 2, 3, 4, 5, 6)),
+                               rtol=1e-11)
