@@ -274,6 +274,28 @@ int dp_point_sources(dp_ctx* ctx, const int site[4], int c0, int ncols, void* et
 int dp_apply_dev_slots(dp_ctx* ctx, const void* in_dev, void* out_dev, int nrhs, int flags, const double* M,
                        const double* alpha, void* hip_stream);
 
+/* For the callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * dp_apply_dev with the same arguments, flags and result, but every
+ * temporary (the parity fields, their inner-precision copies, the per-slot
+ * tables) lives in a static device array of DP_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends; the call
+ * allocates nothing (no hipMalloc, hipFree or other allocating routine) and
+ * records no launch timing.  Limits: 1 <= nrhs <= DP_NOALLOC_MAX_RHS, and the
+ * temporaries must fit the array, else DP_ERR_INVALID_ARG with both sizes in
+ * dp_last_error: per right-hand side 5 FP64 parity fields (V/2 * 192 bytes
+ * each) for DP_APPLY_* in FP64, 4 FP64 and 5 inner-precision ones otherwise;
+ * e.g. one 16^3x32 right-hand side in FP32 needs 82 MB, one 24^3x48 one
+ * 414 MB (too large).  DP_APPLY_SCHUR uses the inverse clover of the ctx's
+ * current mass, which an earlier dp_apply, dp_apply_dev or solve with that
+ * mass must have built, else DP_ERR_BAD_STATE.  Every call on one GPU shares
+ * that GPU's array and leaves its contents there: calls that overlap on one
+ * GPU (several host threads, or contexts used concurrently) race and must be
+ * serialised by the caller. */
+#define DP_NOALLOC_SCRATCH_BYTES (128u << 20)
+#define DP_NOALLOC_MAX_RHS 64
+int dp_apply_dev_noalloc(dp_ctx* ctx, const void* in_dev, void* out_dev, int nrhs, int flags, void* hip_stream);
+
 /* ------------------------------------------------------------------ batches
  * A batch is a fixed set of nslots slots on one ctx, each solving one
  * right-hand side with its own mass, alpha profile, residue and source

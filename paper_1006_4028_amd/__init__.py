@@ -150,6 +150,23 @@ class Lattice:
                                                _ptr(m) if m is not None else None, _ptr(a) if a is not None else None,
                                                ctypes.c_void_p(stream)))
 
+    def apply_dev_noalloc(self, in_t, out_t, precond=False, dagger=False, hop_only=False, schur=False,
+                          precision="f64"):
+        """apply_dev through dp_apply_dev_noalloc: the library allocates nothing
+        (its temporaries live in a static device scratch array per GPU)."""
+        import torch
+        assert in_t.is_cuda and out_t.is_cuda and in_t.is_contiguous() and out_t.is_contiguous()
+        assert in_t.dtype == torch.complex128 and out_t.dtype == torch.complex128
+        n = in_t.numel() // (self.V * 12)
+        assert n * self.V * 12 == in_t.numel() and out_t.numel() == in_t.numel()
+        flags = (L.DP_PRECOND if precond else 0) | (L.DP_DAGGER if dagger else 0)
+        flags |= (L.DP_HOP_ONLY if hop_only else 0) | (L.DP_APPLY_SCHUR if schur else 0)
+        flags |= {"f64": 0, "f32": L.DP_APPLY_F32, "f16": L.DP_APPLY_F16}[precision]
+        stream = torch.cuda.current_stream(in_t.device).cuda_stream
+        self._check(self._L.dp_apply_dev_noalloc(self._h, ctypes.c_void_p(in_t.data_ptr()),
+                                                 ctypes.c_void_p(out_t.data_ptr()), n, flags,
+                                                 ctypes.c_void_p(stream)))
+
     def point_sources(self, site, c0=0, ncols=12, out=None):
         """Unit point sources at `site` in spin-colour components c0 .. c0+ncols-1,
         written by dp_point_sources into a complex128 CUDA tensor [ncols, V*12]

@@ -24,13 +24,14 @@ DP_PREC = {"f64": 0, "f32": 1, "f16": 2, "f32single": 3}
 DP_SOLVER = {"bicgstab": 0, "cgnr": 1}
 
 DP_PRECOND, DP_DAGGER, DP_HOP_ONLY = 1, 2, 4
+DP_NOALLOC_SCRATCH_BYTES, DP_NOALLOC_MAX_RHS = 128 << 20, 64
 # test hooks of dp_apply (documented in include/dp.h)
 DP_APPLY_SCHUR, DP_APPLY_F32, DP_APPLY_F16 = 8, 16, 32
 
 EXPORTED = [
     "dp_create", "dp_destroy", "dp_last_error", "dp_set_gauge", "dp_set_gauge_dev", "dp_set_clover",
     "dp_set_clover_field", "dp_set_mass", "dp_set_kappa", "dp_set_alpha", "dp_set_alpha_space", "dp_apply",
-    "dp_apply_dev", "dp_apply_dev_slots", "dp_point_sources", "dp_solve", "dp_solve_sap",
+    "dp_apply_dev", "dp_apply_dev_slots", "dp_apply_dev_noalloc", "dp_point_sources", "dp_solve", "dp_solve_sap",
     "dp_solve_dev", "dp_footprint_bytes", "dp_set_timing", "dp_get_timing", "dp_get_timing_samples",
     "dp_batch_open", "dp_batch_close",
     "dp_batch_admit", "dp_batch_step", "dp_batch_harvest", "dp_batch_status", "dp_batch_device_bytes",
@@ -106,6 +107,7 @@ def lib():
     L.dp_apply.argtypes = [vp, dp, dp, ctypes.c_int]
     L.dp_apply_dev.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
     L.dp_apply_dev_slots.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, dp, dp, vp]
+    L.dp_apply_dev_noalloc.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
     L.dp_point_sources.argtypes = [vp, ip, ctypes.c_int, ctypes.c_int, vp, vp]
     L.dp_solve.argtypes = [vp, dp, ctypes.c_int, ctypes.POINTER(dp_params), dp, dp, ctypes.POINTER(dp_info)]
     L.dp_solve_dev.argtypes = [vp, vp, ctypes.c_int, ctypes.POINTER(dp_params), vp, dp,

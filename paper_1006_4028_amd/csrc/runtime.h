@@ -10,22 +10,31 @@
 
 namespace dp {
 
-// Owned device allocation.
+// Owned device allocation, or a view of memory owned elsewhere (view()).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool owned = true;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+  }
+  // a view of n bytes at q (never freed here, never grown)
+  void view(void* q, size_t n) {
+    release();
+    p = q;
+    bytes = n;
+    owned = false;
   }
   // grow to at least n bytes (contents not preserved)
   hipError_t reserve(size_t n) {
     if (n <= bytes) return hipSuccess;
+    if (!owned) return hipErrorInvalidValue;  // a view cannot grow
     release();
     hipError_t e = hipMalloc(&p, n);
     if (e != hipSuccess) {
@@ -135,6 +144,11 @@ struct dp_ctx {
   bool has_space = false;
 
   dp::Workspace ws_apply;           // for dp_apply / dp_apply_dev
+  // dp_apply_dev_noalloc: views into this device's static scratch array and a
+  // host staging area sized at creation
+  void* scratch_dev = nullptr;
+  dp::Workspace ws_noalloc;
+  std::vector<double> na_host;
   std::vector<double> apply_key;    // what ws_apply's per-slot tables were built for
   dp_batch* solve_batch = nullptr;  // reused by dp_solve
   dp::SapState* sap = nullptr;      // dp_solve_sap

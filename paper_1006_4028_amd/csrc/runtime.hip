@@ -10,6 +10,8 @@
 #include <cstdio>
 #include <cstring>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 #include <new>
 
 #include "runtime.h"
@@ -516,6 +518,10 @@ int set_gauge_common(dp_ctx* c, const double2* Udev, hipStream_t st) {
 
 }  // namespace
 
+namespace {
+int scratch_setup(dp_ctx* c);
+}  // namespace
+
 // ===================================================================== C ABI
 
 extern "C" {
@@ -555,8 +561,14 @@ int dp_create(const int dims[4], int bc_t, int device, dp_ctx** out) {
     return DP_ERR_DEVICE;
   }
   c->alpha.assign(g.T, 1.0);
+  // dp_apply_dev_noalloc: this device's scratch address and the host staging
+  // of its per-slot tables (ratio tables, T ones, masses, unit scales, pointers)
+  c->na_host.assign((size_t)(4 * g.T + 2 + 4) * DP_NOALLOC_MAX_RHS + g.T, 0.0);
+  for (int q = 0; q < 3; ++q) c->ws_noalloc.h_ainv[q].assign(DP_NOALLOC_MAX_RHS, nullptr);
+  c->ws_noalloc.h_ainv_scale.assign(DP_NOALLOC_MAX_RHS, nullptr);
   const double* none[3] = {nullptr, nullptr, nullptr};
-  int rc = upload_space(c, none);
+  int rc = scratch_setup(c);
+  if (rc == DP_OK) rc = upload_space(c, none);
   if (rc == DP_OK) rc = set_gauge_common(c, nullptr, c->stream);  // unit links, no clover
   if (rc != DP_OK) {
     delete c;
@@ -694,6 +706,8 @@ int check_apply_flags(dp_ctx* c, int flags) {
   return DP_OK;
 }
 
+int apply_run(dp_ctx* c, Workspace& w, const double2* in, double2* out, int n, int flags);
+
 // The operator on n device spinors in host layout (in and out may not alias),
 // enqueued on the ctx stream.  Slot k has the mass Ms[k] and the time profile
 // alphas[k * T ..] (null: the ctx's for every slot).  The per-slot tables are
@@ -702,7 +716,6 @@ int check_apply_flags(dp_ctx* c, int flags) {
 int apply_core(dp_ctx* c, const double2* in, double2* out, int n, int flags, const double* Ms = nullptr,
                const double* alphas = nullptr) {
   const int prec = (flags & DP_APPLY_F32) ? F32 : (flags & DP_APPLY_F16) ? F16 : F64;
-  const int dag = (flags & DP_DAGGER) ? 1 : 0;
   Workspace& w = c->ws_apply;
   DP_TRY(ensure_ws(c, w, n, prec));
   w.sratio = (flags & DP_PRECOND) && c->has_space ? space_ratios(c, 1) : nullptr;
@@ -743,6 +756,17 @@ int apply_core(dp_ctx* c, const double2* in, double2* out, int n, int flags, con
     std::copy(s16.begin(), s16.end(), w.h_ainv_scale.begin());
     c->apply_key = key;
   }
+  return apply_run(c, w, in, out, n, flags);
+}
+
+// The launches of the operator on n device spinors (host layout) with the
+// per-slot tables of w already in place: import into parity fields, the
+// inner-precision copies, the hop kernels (full, Schur or hop-only operator),
+// the FP64 copies and the export.
+int apply_run(dp_ctx* c, Workspace& w, const double2* in, double2* out, int n, int flags) {
+  const int prec = (flags & DP_APPLY_F32) ? F32 : (flags & DP_APPLY_F16) ? F16 : F64;
+  const int dag = (flags & DP_DAGGER) ? 1 : 0;
+  const Geom& g = c->g;
   const long col = 2L * g.Vh * 12;  // double2 per column
   DP_HIP(c, launch_spinor_import(g, in, n, col, 0, w.eta_e.ref(), nullptr, nullptr, c->stream));
   DP_HIP(c, launch_spinor_import(g, in, n, col, 1, w.eta_o.ref(), nullptr, nullptr, c->stream));
@@ -777,9 +801,186 @@ int apply_core(dp_ctx* c, const double2* in, double2* out, int n, int flags, con
   return DP_OK;
 }
 
+// ------------------------------------------------------------ no-alloc apply
+//
+// dp_apply_dev_noalloc keeps every temporary of dp_apply_dev (the parity
+// fields, their inner-precision copies and the per-slot tables) in `scratch`,
+// a static device array the loader places on every GPU the library runs on.
+// Host code never passes the array's name anywhere: it is a host-side
+// stand-in for the symbol.  The device address comes from
+// hipGetSymbolAddress, once per device with that device current (at
+// dp_create), and only that address is used.
+
+__device__ __align__(256) unsigned char scratch[DP_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;  // device -> address of its copy of `scratch`
+
+int scratch_setup(dp_ctx* c) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(c->device);
+  if (it == g_scratch_addr.end()) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(c, e, "hipGetSymbolAddress(scratch)", __LINE__);
+    if (!ptr) return fail(c, DP_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned a null address");
+    it = g_scratch_addr.emplace(c->device, ptr).first;
+  }
+  c->scratch_dev = it->second;
+  return DP_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Byte offsets in the scratch for n right-hand sides at precision prec.
+struct NoallocLayout {
+  size_t f64[5];  // eta_e, eta_o, b64, to64, to (to: FP64 only)
+  size_t in[5], in_scale[5];  // r, s, v, t, to in the inner precision (and FP16 scales)
+  size_t ratio, m4, sscale, ainv[3], ainv_scale, end;
+};
+
+NoallocLayout noalloc_layout(const Geom& g, int n, int prec) {
+  NoallocLayout L{};
+  size_t off = 0;
+  const size_t f64 = align256((size_t)n * g.Vp * spinor_site_bytes(F64));
+  for (int k = 0; k < 5; ++k) {
+    L.f64[k] = off;
+    if (k < 4 || prec == F64) off += f64;
+  }
+  if (prec != F64) {
+    const size_t fin = align256((size_t)n * g.Vp * spinor_site_bytes(prec));
+    const size_t fsc = prec == F16 ? align256((size_t)n * g.Vp * sizeof(float)) : 0;
+    for (int k = 0; k < 5; ++k) {
+      L.in[k] = off;
+      off += fin;
+      L.in_scale[k] = off;
+      off += fsc;
+    }
+  }
+  L.ratio = off;
+  off += align256(sizeof(double) * 4 * g.T * n);
+  L.m4 = off;
+  off += align256(sizeof(double) * n);
+  L.sscale = off;
+  off += align256(sizeof(double) * n);
+  for (int q = 0; q < 3; ++q) {
+    L.ainv[q] = off;
+    off += align256(sizeof(void*) * n);
+  }
+  L.ainv_scale = off;
+  off += align256(sizeof(float*) * n);
+  L.end = off;
+  return L;
+}
+
+void field_view(Field& f, const Geom& g, int prec, int n, char* data, char* scale) {
+  f.prec = prec;
+  f.nslots = n;
+  f.slot_stride = (long)g.Vp * (prec == F64 ? 12 : prec == F32 ? 6 : 3);
+  f.scale_stride = prec == F16 ? g.Vp : 0;
+  f.data.view(data, (size_t)n * g.Vp * spinor_site_bytes(prec));
+  if (prec == F16) f.scale.view(scale, (size_t)n * g.Vp * sizeof(float));
+  else f.scale.view(nullptr, 0);
+}
+
 }  // namespace
 
 extern "C" {
+
+int dp_apply_dev_noalloc(dp_ctx* c, const void* in, void* out, int nrhs, int flags, void* stream) {
+  if (!c || !in || !out) return fail(c, DP_ERR_INVALID_ARG, "null argument");
+  if (nrhs <= 0 || nrhs > DP_NOALLOC_MAX_RHS) return fail(c, DP_ERR_INVALID_ARG, "nrhs must be in [1, DP_NOALLOC_MAX_RHS]");
+  DP_TRY(check_apply_flags(c, flags));
+  const Geom& g = c->g;
+  const size_t bytes = (size_t)nrhs * 2 * g.Vh * 12 * sizeof(double2);
+  const char* a = static_cast<const char*>(in);
+  const char* b = static_cast<const char*>(out);
+  if (a < b + bytes && b < a + bytes) return fail(c, DP_ERR_INVALID_ARG, "in and out overlap");
+  if (!c->scratch_dev) return fail(c, DP_ERR_BAD_STATE, "no scratch address for this device");
+  const int prec = (flags & DP_APPLY_F32) ? F32 : (flags & DP_APPLY_F16) ? F16 : F64;
+  const NoallocLayout lay = noalloc_layout(g, nrhs, prec);
+  if (lay.end > (size_t)DP_NOALLOC_SCRATCH_BYTES) {
+    char msg[200];
+    snprintf(msg, sizeof msg, "%d right-hand sides of this lattice need %zu bytes of scratch; it holds %zu", nrhs,
+             lay.end, (size_t)DP_NOALLOC_SCRATCH_BYTES);
+    return fail(c, DP_ERR_INVALID_ARG, msg);
+  }
+  DP_HIP(c, hipSetDevice(c->device));
+  DP_TRY(check_state(c));
+  // the inverse clover of the current mass is only looked up, never built
+  MassEntry* me = nullptr;
+  for (auto* m : c->masses)
+    if (m->M == c->M) me = m;
+  if (!me && (flags & DP_APPLY_SCHUR))
+    return fail(c, DP_ERR_BAD_STATE,
+                "the inverse clover of the current mass is not built: call dp_apply_dev (or a solve) with this "
+                "mass once before");
+  if (stream) DP_HIP(c, hipStreamSynchronize((hipStream_t)stream));
+  // views into the scratch
+  Workspace& w = c->ws_noalloc;
+  char* base = static_cast<char*>(c->scratch_dev);
+  Field* f64[5] = {&w.eta_e, &w.eta_o, &w.b64, &w.to64, &w.to};
+  for (int k = 0; k < 5; ++k)
+    if (k < 4 || prec == F64) field_view(*f64[k], g, F64, nrhs, base + lay.f64[k], nullptr);
+  if (prec != F64) {
+    Field* fin[5] = {&w.r, &w.s, &w.v, &w.t, &w.to};
+    for (int k = 0; k < 5; ++k) field_view(*fin[k], g, prec, nrhs, base + lay.in[k], base + lay.in_scale[k]);
+  }
+  w.ratio.view(base + lay.ratio, sizeof(double) * 4 * g.T * nrhs);
+  w.m4.view(base + lay.m4, sizeof(double) * nrhs);
+  w.slot_scale.view(base + lay.sscale, sizeof(double) * nrhs);
+  for (int q = 0; q < 3; ++q) w.ainv_ptr[q].view(base + lay.ainv[q], sizeof(void*) * nrhs);
+  w.ainv_scale_ptr.view(base + lay.ainv_scale, sizeof(float*) * nrhs);
+  w.nslots = nrhs;
+  w.prec = prec;
+  w.sratio = (flags & DP_PRECOND) && c->has_space ? space_ratios(c, 1) : nullptr;
+  // per-slot tables, staged in the host area sized at dp_create
+  double* h = c->na_host.data();
+  const double* alpha = (flags & DP_PRECOND) ? c->alpha.data() : nullptr;
+  for (int k = 0; k < nrhs; ++k) {
+    double* rt = h + (size_t)4 * g.T * k;
+    if (alpha) {
+      ratio_tables(g.T, c->bc_t, alpha, rt);
+    } else {
+      double* ones = h + (size_t)4 * g.T * nrhs;  // T ones after the tables
+      for (int t = 0; t < g.T; ++t) ones[t] = 1.0;
+      ratio_tables(g.T, c->bc_t, ones, rt);
+    }
+  }
+  double* m4 = h + (size_t)4 * g.T * nrhs + g.T;
+  double* one = m4 + nrhs;
+  const void** ptrs = reinterpret_cast<const void**>(one + nrhs);  // 4 nrhs pointers
+  for (int k = 0; k < nrhs; ++k) {
+    m4[k] = 4.0 + c->M;
+    one[k] = 1.0;
+    ptrs[k] = me ? me->a64.p : nullptr;
+    ptrs[nrhs + k] = me ? me->a32.p : nullptr;
+    ptrs[2 * nrhs + k] = me ? me->a16.p : nullptr;
+    ptrs[3 * nrhs + k] = me ? me->s16.p : nullptr;
+    for (int q = 0; q < 3; ++q) w.h_ainv[q][k] = ptrs[q * nrhs + k];
+    w.h_ainv_scale[k] = static_cast<const float*>(ptrs[3 * nrhs + k]);
+  }
+  for (int k = nrhs; k < (int)w.h_ainv_scale.size(); ++k) {  // entries beyond this call's slots
+    for (int q = 0; q < 3; ++q) w.h_ainv[q][k] = nullptr;
+    w.h_ainv_scale[k] = nullptr;
+  }
+  DP_HIP(c, hipMemcpyAsync(w.ratio.p, h, sizeof(double) * 4 * g.T * nrhs, hipMemcpyHostToDevice, c->stream));
+  DP_HIP(c, hipMemcpyAsync(w.m4.p, m4, sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
+  DP_HIP(c, hipMemcpyAsync(w.slot_scale.p, one, sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
+  for (int q = 0; q < 3; ++q)
+    DP_HIP(c, hipMemcpyAsync(w.ainv_ptr[q].p, ptrs + q * nrhs, sizeof(void*) * nrhs, hipMemcpyHostToDevice,
+                             c->stream));
+  DP_HIP(c, hipMemcpyAsync(w.ainv_scale_ptr.p, ptrs + 3 * nrhs, sizeof(float*) * nrhs, hipMemcpyHostToDevice,
+                           c->stream));
+  // no launch timing here (it creates events and records into host maps)
+  const bool timing = c->timing;
+  c->timing = false;
+  const int rc = apply_run(c, w, static_cast<const double2*>(in), static_cast<double2*>(out), nrhs, flags);
+  c->timing = timing;
+  DP_TRY(rc);
+  DP_HIP(c, hipStreamSynchronize(c->stream));
+  return DP_OK;
+}
 
 int dp_apply(dp_ctx* c, const double* in, double* out, int flags) {
   if (!c || !in || !out) return fail(c, DP_ERR_INVALID_ARG, "null argument");
