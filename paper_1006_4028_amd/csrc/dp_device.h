@@ -307,6 +307,73 @@ struct SpinorIO<F16> {
   }
 };
 
+// ------------------------------------------------------------ raw spinors
+//
+// A neighbour spinor as stored (no conversion), so that the loads of several
+// neighbours can be issued before the first is used; decode() converts it
+// and returns the factor its components carry (the FP16 per-site scale, else 1).
+
+template <int P>
+struct RawSpinor;
+template <>
+struct RawSpinor<F64> {
+  double2 v[12];
+};
+template <>
+struct RawSpinor<F32> {
+  float4 v[6];
+};
+template <>
+struct RawSpinor<F16> {
+  uint4 v[3];
+  float sc;
+};
+
+template <int P>
+__device__ __forceinline__ void load_raw_spinor(const SpinorRef& f, int slot, int i, int Vh, RawSpinor<P>& r) {
+  if constexpr (P == F64) {
+    const double2* b = static_cast<const double2*>(f.data) + (long)slot * f.slot_stride;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) r.v[c] = b[(long)c * Vh + i];
+  } else if constexpr (P == F32) {
+    const float4* b = static_cast<const float4*>(f.data) + (long)slot * f.slot_stride;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.v[k] = b[(long)k * Vh + i];
+  } else {
+    const uint4* b = static_cast<const uint4*>(f.data) + (long)slot * f.slot_stride;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r.v[k] = b[(long)k * Vh + i];
+    r.sc = f.scale[(long)slot * f.scale_stride + i];
+  }
+}
+
+// the same values and factor SpinorIO<P>::load_unscaled gives
+template <int P, typename R>
+__device__ __forceinline__ R decode_spinor(const RawSpinor<P>& r, cx<R> (&s)[12]) {
+  if constexpr (P == F64) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) s[c] = cx<R>{(R)r.v[c].x, (R)r.v[c].y};
+    return R(1);
+  } else if constexpr (P == F32) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      s[2 * k] = cx<R>{(R)r.v[k].x, (R)r.v[k].y};
+      s[2 * k + 1] = cx<R>{(R)r.v[k].z, (R)r.v[k].w};
+    }
+    return R(1);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float2 a0 = h2f(r.v[k].x), a1 = h2f(r.v[k].y), a2 = h2f(r.v[k].z), a3 = h2f(r.v[k].w);
+      s[4 * k + 0] = cx<R>{(R)a0.x, (R)a0.y};
+      s[4 * k + 1] = cx<R>{(R)a1.x, (R)a1.y};
+      s[4 * k + 2] = cx<R>{(R)a2.x, (R)a2.y};
+      s[4 * k + 3] = cx<R>{(R)a3.x, (R)a3.y};
+    }
+    return (R)r.sc;
+  }
+}
+
 // ------------------------------------------------------------ links
 
 template <int P>
@@ -440,7 +507,8 @@ struct CloverIO<F16> {
 #pragma unroll
       for (int k = 0; k < 6; ++k) B[h].d[k] = (R)(r[36 * h + k] * sc);
 #pragma unroll
-      for (int k = 0; k < 15; ++k) B[h].o[k] = cx<R>{(R)(r[36 * h + 6 + 2 * k] * sc), (R)(r[36 * h + 7 + 2 * k] * sc)};
+      for (int k = 0; k < 15; ++k)
+        B[h].o[k] = cx<R>{(R)(r[36 * h + 6 + 2 * k] * sc), (R)(r[36 * h + 7 + 2 * k] * sc)};
     }
   }
   template <typename R>

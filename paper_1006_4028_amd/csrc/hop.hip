@@ -25,6 +25,7 @@
 // ("slots"); the links of the site are loaded once for the group.
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #include "dp_device.h"
 
@@ -167,6 +168,136 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const int (&sl)[NS], c
       link_dag_mul(u, h, w);
       accumulate<MU, -S>(acc[k], w, (MU == 0 ? cb[k] : sb) * sc);
     }
+  }
+}
+
+// ---------------------------------------------------------------- batched
+// The shared-tile kernel's hop for one slot, neighbour by neighbour in the
+// order of hop_dir (K = 2 mu forward, 2 mu + 1 backward) and with its
+// arithmetic, but the loads of PF neighbours are issued together before the
+// first of them is used (a scheduling barrier keeps the compiler from
+// spreading them out again): more bytes in flight per wave.
+
+// Number of neighbours whose loads are issued together, per storage precision.
+#ifndef DP_SHARED_PF32
+#define DP_SHARED_PF32 4
+#endif
+#ifndef DP_SHARED_PF16
+#define DP_SHARED_PF16 4
+#endif
+template <int P>
+constexpr int shared_pf() {
+  return P == F16 ? DP_SHARED_PF16 : P == F32 ? DP_SHARED_PF32 : 2;
+}
+
+// The slab kernel can run the same batched code with the links read from
+// memory (prefetched with the spinors); off by default (DP_SLAB_PF32 = 0:
+// the per-direction code).
+#ifndef DP_SLAB_PF32
+#define DP_SLAB_PF32 0
+#endif
+template <int P>
+constexpr int slab_pf() {
+  return P == F32 ? DP_SLAB_PF32 : 0;
+}
+
+template <int P>
+struct RawLink;
+template <>
+struct RawLink<F64> {
+  double2 v[9];
+};
+template <>
+struct RawLink<F32> {
+  float2 v[9];
+};
+template <>
+struct RawLink<F16> {
+  unsigned v[9];
+};
+
+template <int P>
+__device__ __forceinline__ void load_raw_link(const void* base, int mu, int i, int Vh, RawLink<P>& r) {
+  using T = decltype(r.v[0]);
+  using E = typename std::remove_reference<T>::type;
+  const E* b = static_cast<const E*>(base) + (long)mu * 9 * Vh;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) r.v[k] = b[(long)k * Vh + i];
+}
+
+template <int P, typename R>
+__device__ __forceinline__ void decode_link(const RawLink<P>& r, cx<R> (&u)[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    if constexpr (P == F16) {
+      const float2 v = h2f(r.v[k]);
+      u[k] = cx<R>{(R)v.x, (R)v.y};
+    } else {
+      u[k] = cx<R>{(R)r.v[k].x, (R)r.v[k].y};
+    }
+  }
+}
+
+template <int P, int K, bool DAG, bool LDSL>
+__device__ __forceinline__ void nb_compute(const RawSpinor<P>& raw, const RawLink<P>& rl, typename Tr<P>::R coef,
+                                           const cx<typename Tr<P>::R>* lu, int lane,
+                                           cx<typename Tr<P>::R> (&acc)[12]) {
+  using R = typename Tr<P>::R;
+  constexpr int MU = K >> 1;
+  constexpr bool FWD = (K & 1) == 0;
+  constexpr int S = (DAG ? -1 : 1) * (FWD ? 1 : -1);
+  cx<R> psi[12], u[9];
+  Half<R> h, w;
+  if constexpr (LDSL) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = lu[(K * 9 + k) * 64 + lane];
+  } else {
+    decode_link<P>(rl, u);
+  }
+  const R sc = decode_spinor<P>(raw, psi);
+  project<MU, S>(psi, h);
+  if constexpr (FWD) link_mul(u, h, w);
+  else link_dag_mul(u, h, w);
+  accumulate<MU, S>(acc, w, coef * sc);
+}
+
+template <int P, int K, int END, bool DAG, bool LDSL>
+struct NbSeq {
+  __device__ static __forceinline__ void run(const RawSpinor<P>* raw, const RawLink<P>* rl,
+                                             const typename Tr<P>::R (&coef)[8], const cx<typename Tr<P>::R>* lu,
+                                             int lane, cx<typename Tr<P>::R> (&acc)[12]) {
+    nb_compute<P, K, DAG, LDSL>(raw[0], rl[0], coef[K], lu, lane, acc);
+    NbSeq<P, K + 1, END, DAG, LDSL>::run(raw + 1, rl + 1, coef, lu, lane, acc);
+  }
+};
+template <int P, int END, bool DAG, bool LDSL>
+struct NbSeq<P, END, END, DAG, LDSL> {
+  __device__ static __forceinline__ void run(const RawSpinor<P>*, const RawLink<P>*, const typename Tr<P>::R (&)[8],
+                                             const cx<typename Tr<P>::R>*, int, cx<typename Tr<P>::R> (&)[12]) {}
+};
+
+// LDSL: links from the workgroup's LDS copy, else loaded with the spinors
+// (forward hops from U_out at the output site, backward ones from U_in at the
+// neighbour).
+template <int P, int K0, int PF, bool DAG, bool LDSL>
+__device__ __forceinline__ void nb_batches(const HopArgs& a, int slot, int i, const int (&nb)[8],
+                                           const typename Tr<P>::R (&coef)[8], const cx<typename Tr<P>::R>* lu,
+                                           int lane, cx<typename Tr<P>::R> (&acc)[12]) {
+  if constexpr (K0 < 8) {
+    RawSpinor<P> raw[PF];
+    RawLink<P> rl[PF];  // unused (and eliminated) with LDS links
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      load_raw_spinor<P>(a.in, slot, nb[K0 + q], a.g.Vp, raw[q]);
+      if constexpr (!LDSL) {
+        const int K = K0 + q;
+        if ((K & 1) == 0) load_raw_link<P>(a.U_out, K >> 1, i, a.g.Vp, rl[q]);
+        else load_raw_link<P>(a.U_in, K >> 1, nb[K], a.g.Vp, rl[q]);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    NbSeq<P, K0, K0 + PF, DAG, LDSL>::run(raw, rl, coef, lu, lane, acc);
+    nb_batches<P, K0 + PF, PF, DAG, LDSL>(a, slot, i, nb, coef, lu, lane, acc);
   }
 }
 
@@ -319,10 +450,29 @@ __device__ __forceinline__ void site_work(const HopArgs& a, int grp, int i, bool
         off += 4 * Ls[k];
       }
     }
-    hop_dir<P, 0, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
-    hop_dir<P, 1, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
-    hop_dir<P, 2, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
-    hop_dir<P, 3, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
+    constexpr int PF = LDS ? shared_pf<P>() : slab_pf<P>();
+    if constexpr (NS == 1 && PF > 0) {
+      // neighbour loads issued in batches (the shared-tile kernel, and the
+      // one-slot FP32 slab kernel with the same arithmetic)
+      const Geom& gg = a.g;
+      const int Ls[4] = {gg.T, gg.L1, gg.L2, gg.L3};
+      int nb[8];
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) {
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        y[mu] = x[mu] + 1 == Ls[mu] ? 0 : x[mu] + 1;
+        nb[2 * mu] = eo_index(gg, y[0], y[1], y[2], y[3]);
+        y[mu] = x[mu] == 0 ? Ls[mu] - 1 : x[mu] - 1;
+        nb[2 * mu + 1] = eo_index(gg, y[0], y[1], y[2], y[3]);
+      }
+      const R coef[8] = {cf[0], cb[0], sp[0], sp[1], sp[2], sp[3], sp[4], sp[5]};
+      if (on[0]) nb_batches<P, 0, PF, DAG, LDS>(a, sl[0], i, nb, coef, lu, lane, acc[0]);
+    } else {
+      hop_dir<P, 0, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
+      hop_dir<P, 1, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
+      hop_dir<P, 2, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
+      hop_dir<P, 3, NS, DAG, LDS>(a, sl, on, i, x, cf, cb, sp, acc, lu, lane);
+    }
 #pragma unroll
     for (int k = 0; k < NS; ++k)
       if (on[k]) epilogue<P, EPI, RED, NT, LDS, LINV>(a, sl[k], i, acc[k], red[k], lc, lane);
@@ -423,10 +573,18 @@ constexpr size_t shared_tile_bytes(bool clover) {
 // for its neighbour loads (at three waves per SIMD the compiler spills): its
 // workgroups have 4 waves with two waves per SIMD (256 registers), two
 // workgroups per CU.
+#ifndef DP_SHARED_WG32
+#define DP_SHARED_WG32 256
+#endif
+#ifndef DP_SHARED_MINW32
+#define DP_SHARED_MINW32 2
+#endif
 template <int P>
-constexpr int shared_max_threads(int red) { return P == F16 ? 256 : red == RED_TS4 ? 512 : 768; }
+constexpr int shared_max_threads(int red) {
+  return P == F16 ? 256 : red == RED_TS4 ? 512 : DP_SHARED_WG32;
+}
 template <int P>
-constexpr int shared_min_waves() { return P == F16 ? 2 : 1; }
+constexpr int shared_min_waves() { return P == F16 ? 2 : DP_SHARED_MINW32; }
 
 // The staged links and blocks are read once per launch: streamed past L2
 // (measured on MI355X at 24^3x48 with 12 slots: 2-3% faster).
@@ -555,13 +713,17 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
     // then takes 250 registers per lane).  Tuning knob: DP_HOP_SHARED = 0
     // keeps one workgroup per slot group.
     static const bool shared = env_knob("DP_HOP_SHARED", 1) == 1;
-    // FP16 storage through the shared-tile kernel: the links and the scaled
-    // clover values are converted to FP32 once in LDS, so the per-slot work is
-    // the FP32 kernel's plus the FP16 neighbour loads.  Tuning knob:
-    // DP_HOP_SHARED16 = 0 keeps the slab kernel for FP16.
-    static const bool shared16 = env_knob("DP_HOP_SHARED16", 1) == 1;
-    if constexpr (P == F32 || P == F16) {
-      if (shared && (P == F32 || shared16) && nt && a.nslots >= 2 && !forced) {
+    // FP16 storage keeps the slab kernel: through the shared-tile kernel
+    // (links and scaled clover values converted to FP32 once in LDS, 4-wave
+    // workgroups at two waves per SIMD) it was measured on MI355X at 24^3x48
+    // with 12 slots 8-14% faster, but with the fixed fused-multiply-add
+    // arithmetic it needs more than 256 registers and spills.
+    // FP32 runs the shared-tile kernel for any number of slots, one slot
+    // alone included: a slot's arithmetic is then the same code whatever the
+    // batch it is in, so its results are bitwise the same alone and in any
+    // mix (with a single slot the workgroup is one wave).
+    if constexpr (P == F32) {
+      if (shared && nt && !forced) {
         m.ngroups = a.nslots;
         // waves per workgroup: the fewest passes of at most 12 waves, one
         // 12-wave workgroup per CU (three waves per SIMD): half as many
