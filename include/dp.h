@@ -130,9 +130,39 @@ int dp_set_gauge(dp_ctx* ctx, const double* U);
 /* Same from device memory of the ctx's GPU. */
 int dp_set_gauge_dev(dp_ctx* ctx, const void* U_dev, void* hip_stream);
 
+/* Paper: the closing remark of the heavy-quark section (the Schroedinger
+ * functional, where correlators decay over the whole time extent).
+ * For a ctx created with bc_t = 0, whose T timeslices are the interior
+ * 1 <= x0 <= T of a Schroedinger-functional lattice with boundaries at
+ * x0 = 0 and x0 = T + 1: U_ext holds the links of the whole lattice, host
+ * layout with T + 2 timeslices (index 0: the boundary x0 = 0, 1..T: the
+ * interior, T + 1: the boundary x0 = T + 1).  The interior links become the
+ * ctx's gauge field (as dp_set_gauge); the spatial links of the two
+ * boundaries (the boundary gauge fields) and the time links between them
+ * and the interior enter the clover term next to the boundaries, which
+ * dp_set_clover builds from the whole lattice; the time links on x0 = 0 give
+ * the boundary sources of dp_sf_wall_sources.  ct_tilde is the coefficient
+ * of the fermion boundary counterterm: (ct_tilde - 1) psi on the first and
+ * last interior timeslices (1: none), in force from this call on.  The
+ * fermion field vanishes on the boundaries (the hops into them drop).
+ * DP_ERR_BAD_STATE on a ctx with bc_t != 0. */
+int dp_set_gauge_sf(dp_ctx* ctx, const double* U_ext, double ct_tilde);
+
+/* Paper: as dp_set_gauge_sf.
+ * The boundary sources of the Schroedinger functional into eta_dev (device,
+ * ncols full-lattice spinors, host layout): column j is
+ * U_0(x0 = 0, xs)^+ P+ e_c with c = c0 + j (the unit spin-colour vector),
+ * P+ = (1 + gamma_0)/2, on the first interior timeslice (every spatial site)
+ * and 0 elsewhere: the hop from the boundary field P+ psi(0) = e_c moved to
+ * the right-hand side.  Needs dp_set_gauge_sf (else DP_ERR_BAD_STATE) and
+ * 0 <= c0, c0 + ncols <= 12. */
+int dp_sf_wall_sources(dp_ctx* ctx, int c0, int ncols, void* eta_dev, void* hip_stream);
+
 /* Paper: the O(a)-improved Wilson operator named at the start of the
  * heavy-quark section, with the coefficient c_sw of the Table 1 caption.
- * Clover term c_sw (i/4) sum sigma F from the resident links (built on the GPU). */
+ * Clover term c_sw (i/4) sum sigma F from the resident links (built on the GPU;
+ * with Schroedinger-functional links from the whole padded lattice, plus the
+ * boundary counterterm). */
 int dp_set_clover(dp_ctx* ctx, double csw);
 /* A caller-supplied clover field, host layout [site][12][12]; it must be
  * Hermitian and commute with gamma5 (block diagonal in the two chiralities),

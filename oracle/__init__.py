@@ -260,3 +260,28 @@ def cpp(S, x0_src=0):
     out = np.zeros(dims[0])
     _check(_lib().orc_cpp(_dims(dims), S.shape[0], _ptr(S), int(x0_src), _ptr(out)), "orc_cpp")
     return out
+
+
+def sf_clover(U_ext, csw, ct_tilde=1.0):
+    """Clover term of the interior of a Schroedinger-functional lattice (the
+    closing remark of the heavy-quark section names the formulation).  U_ext
+    holds T + 2 timeslices: the boundary x0 = 0, the interior, the boundary
+    x0 = T + 1.  The clover leaves of an interior site stay within the padded
+    lattice (they reach at most one timeslice beyond the interior), so the
+    clover of the padded lattice, restricted to the interior, is the
+    interior's clover with the boundary links in its leaves; (ct_tilde - 1)
+    is added on the first and last interior timeslices (the fermion boundary
+    counterterm).  Returns C[T, L1, L2, L3, 12, 12]."""
+    C = clover(U_ext, csw)[1:-1].copy()
+    eye = np.eye(12, dtype=np.complex128)
+    C[0] += (ct_tilde - 1.0) * eye
+    C[-1] += (ct_tilde - 1.0) * eye
+    return C
+
+
+def sf_apply(U_ext, csw, M, psi, alpha=None, ct_tilde=1.0, dagger=False):
+    """The Schroedinger-functional operator on the interior field psi: the
+    Dirichlet-boundary operator with the interior links, the clover term of
+    sf_clover and the boundary counterterm (alpha as in apply)."""
+    U = np.ascontiguousarray(np.asarray(U_ext)[1:-1])
+    return apply(U, sf_clover(U_ext, csw, ct_tilde), M, psi, alpha=alpha, bc_t=0, dagger=dagger)

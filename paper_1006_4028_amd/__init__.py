@@ -75,6 +75,25 @@ class Lattice:
         assert U.size == self.V * 36, "gauge field must have T*L1*L2*L3*4*9 entries"
         self._check(self._L.dp_set_gauge(self._h, _ptr(U)))
 
+    def set_gauge_sf(self, U_ext, ct_tilde=1.0):
+        """Schroedinger-functional links: U_ext of shape (T+2, L1, L2, L3, 4, 3, 3),
+        the boundary timeslices first and last (ctx created with bc_t = 0)."""
+        U_ext = _c128(U_ext)
+        assert U_ext.size == (self.T + 2) * (self.V // self.T) * 36
+        self._check(self._L.dp_set_gauge_sf(self._h, _ptr(U_ext), float(ct_tilde)))
+
+    def sf_wall_sources(self, c0=0, ncols=12, out=None):
+        """The boundary sources U_0(0, xs)^+ P+ e_c on the first interior
+        timeslice, as a complex128 CUDA tensor [ncols, V*12]."""
+        import torch
+        if out is None:
+            out = torch.empty((ncols, self.V * 12), dtype=torch.complex128, device="cuda")
+        assert out.is_cuda and out.is_contiguous() and out.numel() == ncols * self.V * 12
+        stream = torch.cuda.current_stream(out.device).cuda_stream
+        self._check(self._L.dp_sf_wall_sources(self._h, int(c0), int(ncols), ctypes.c_void_p(out.data_ptr()),
+                                               ctypes.c_void_p(stream)))
+        return out
+
     def set_clover(self, csw):
         self._check(self._L.dp_set_clover(self._h, float(csw)))
 

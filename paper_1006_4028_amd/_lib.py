@@ -29,7 +29,8 @@ DP_NOALLOC_SCRATCH_BYTES, DP_NOALLOC_MAX_RHS = 128 << 20, 64
 DP_APPLY_SCHUR, DP_APPLY_F32, DP_APPLY_F16 = 8, 16, 32
 
 EXPORTED = [
-    "dp_create", "dp_destroy", "dp_last_error", "dp_set_gauge", "dp_set_gauge_dev", "dp_set_clover",
+    "dp_create", "dp_destroy", "dp_last_error", "dp_set_gauge", "dp_set_gauge_dev", "dp_set_gauge_sf",
+    "dp_sf_wall_sources", "dp_set_clover",
     "dp_set_clover_field", "dp_set_mass", "dp_set_kappa", "dp_set_alpha", "dp_set_alpha_space", "dp_apply",
     "dp_apply_dev", "dp_apply_dev_slots", "dp_apply_dev_noalloc", "dp_point_sources", "dp_solve", "dp_solve_sap",
     "dp_solve_dev", "dp_footprint_bytes", "dp_set_timing", "dp_get_timing", "dp_get_timing_samples",
@@ -97,6 +98,8 @@ def lib():
     L.dp_last_error.restype = ctypes.c_char_p
     L.dp_set_gauge.argtypes = [vp, dp]
     L.dp_set_gauge_dev.argtypes = [vp, vp, vp]
+    L.dp_set_gauge_sf.argtypes = [vp, dp, ctypes.c_double]
+    L.dp_sf_wall_sources.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
     L.dp_set_clover.argtypes = [vp, ctypes.c_double]
     L.dp_set_clover_field.argtypes = [vp, dp]
     L.dp_set_mass.argtypes = [vp, ctypes.c_double]

@@ -299,7 +299,40 @@ __global__ void clover_apply_kernel(Geom g, SlotTable slots, SpinorRef in, Spino
   SpinorIO<F64>::store(out, slot, i, g.Vp, b);
 }
 
+// The interior of a Schroedinger-functional lattice from the clover term
+// built on the lattice padded by one timeslice at each end (the boundaries,
+// which carry the boundary links): interior site (x0, xs) is padded site
+// (x0 + 1, xs), of the other parity and at index i + Vsh there.  ctm1 =
+// ct_tilde - 1 is added to the diagonal of both blocks on the first and last
+// interior timeslices (the fermion boundary counterterm).
+__global__ void clover_sf_interior_kernel(Geom g, Geom gp, const double2* __restrict__ Cpe,
+                                          const double2* __restrict__ Cpo, double ctm1, double2* Ce, double2* Co) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (i >= g.Vh) return;
+  const double2* src = p ? Cpe : Cpo;  // the padded lattice's parity is the other one
+  double2* dst = p ? Co : Ce;
+  const int x0 = i / g.Vsh;
+  const bool edge = x0 == 0 || x0 == g.T - 1;
+  for (int k = 0; k < 36; ++k) {
+    double2 v = src[(long)k * gp.Vp + i + g.Vsh];
+    if (edge && (k % 18) < 3) {
+      v.x += ctm1;
+      v.y += ctm1;
+    }
+    dst[(long)k * g.Vp + i] = v;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_clover_sf_interior(const Geom& g, const Geom& gp, const double2* Cp_eo[2], double ctm1,
+                                     double2* C_eo[2], hipStream_t st) {
+  if (gp.T != g.T + 2 || gp.Vsh != g.Vsh) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(clover_sf_interior_kernel, dim3((g.Vh + kBlock - 1) / kBlock, 2), dim3(kBlock), 0, st, g, gp,
+                     Cp_eo[0], Cp_eo[1], ctm1, C_eo[0], C_eo[1]);
+  return hipGetLastError();
+}
 
 hipError_t launch_clover_apply(const Geom& g, const SlotTable& slots, SpinorRef in, SpinorRef out, int nslots,
                                hipStream_t st) {

@@ -209,6 +209,15 @@ hipError_t launch_spinor_import(const Geom& g, const double2* aos, int nslots, l
 hipError_t launch_spinor_export(const Geom& g, SpinorRef even, SpinorRef odd, int nslots,
                                 const double* alpha_div, const double* sprof, double2* aos, long aos_slot_stride,
                                 hipStream_t stream);
+// Schroedinger functional: the interior clover blocks from those built on the
+// lattice padded with the two boundary timeslices (gp: T + 2 timeslices),
+// plus ctm1 on the diagonal of the first and last interior timeslices.
+hipError_t launch_clover_sf_interior(const Geom& g, const Geom& gp, const double2* Cp_eo[2], double ctm1,
+                                     double2* C_eo[2], hipStream_t stream);
+// Schroedinger functional boundary sources U_0(0, xs)^+ P+ e_c on the first
+// interior timeslice (U0: the time links on x0 = 0, [xs][mu][3][3] complex).
+hipError_t launch_sf_wall_sources(const Geom& g, const double2* U0, int c0, int ncols, double2* out,
+                                  hipStream_t stream);
 // ncols unit point sources (host layout, double2 per complex): column j is 1
 // in spin-colour component c0 + j at site {x0, x1, x2, x3}, 0 elsewhere.
 hipError_t launch_point_sources(const Geom& g, const int site[4], int c0, int ncols, double2* out,

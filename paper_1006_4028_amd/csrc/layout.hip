@@ -142,7 +142,43 @@ __global__ void __launch_bounds__(kBlock) point_source_kernel(long per_col, long
   }
 }
 
+// The boundary sources of the Schroedinger functional: column j is
+// U_0(x0 = 0, xs)^+ P+ e_c, c = c0 + j, on the first interior timeslice and 0
+// elsewhere, with P+ = (1 + gamma_0)/2 of the chiral basis (the projector the
+// backward time hop applies, so that this is the hop from a boundary field
+// P+ psi(0) = e_c).  U0: the time links on x0 = 0, host layout [xs][mu][3][3].
+__global__ void __launch_bounds__(kBlock) sf_wall_source_kernel(long per_col, long Vs, int c0, int ncols,
+                                                                const double2* __restrict__ U0,
+                                                                double2* __restrict__ out) {
+  const long total = per_col * ncols;
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
+    const long j = k / per_col, r = k - j * per_col;
+    const long site = r / 12;
+    const int comp = (int)(r - site * 12), s = comp / 3, a = comp % 3;
+    double2 v = make_double2(0.0, 0.0);
+    if (site < Vs) {  // the first interior timeslice
+      const int c = c0 + (int)j, sc = c / 3, ac = c % 3;
+      // (P+)[s][sc]: 1/2 on the diagonal, -1/2 between spins s and s +- 2
+      const double pp = s == sc ? 0.5 : ((s & 1) == (sc & 1) ? -0.5 : 0.0);
+      const double2 u = U0[(site * 4 + 0) * 9 + ac * 3 + a];  // (U^+)[a][ac] = conj(U[ac][a])
+      v = make_double2(pp * u.x, -pp * u.y);
+    }
+    out[k] = v;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_sf_wall_sources(const Geom& g, const double2* U0, int c0, int ncols, double2* out, hipStream_t st) {
+  if (ncols <= 0 || c0 < 0 || c0 + ncols > 12) return hipErrorInvalidValue;
+  const long per_col = 2L * g.Vh * 12;
+  const long Vs = 2L * g.Vsh;
+  const long total = per_col * ncols;
+  const long blocks = std::min<long>((total + kBlock - 1) / kBlock, 8L * 1024);
+  hipLaunchKernelGGL(sf_wall_source_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, per_col, Vs, c0, ncols, U0,
+                     out);
+  return hipGetLastError();
+}
 
 hipError_t launch_point_sources(const Geom& g, const int site[4], int c0, int ncols, double2* out, hipStream_t st) {
   if (ncols <= 0 || c0 < 0 || c0 + ncols > 12) return hipErrorInvalidValue;

@@ -132,6 +132,12 @@ struct dp_ctx {
   dp::DevBuf C64[2], C32[2], C16[2], C16s[2];
   double csw = 0.0;
   int clover_kind = 0;  // 0: none (c_sw = 0), 1: built from links, 2: caller field
+  // Schroedinger functional (dp_set_gauge_sf): the links of the lattice padded
+  // with the two boundary timeslices (host layout, FP64, on the device) and
+  // the coefficient of the fermion boundary counterterm
+  bool sf = false;
+  double ct_tilde = 1.0;
+  dp::DevBuf sf_ext;
   std::vector<dp::MassEntry*> masses;
   int open_batches = 0;
 

@@ -503,6 +503,8 @@ int clover_convert_all(dp_ctx* c) {
 // Udev == nullptr sets unit links
 int set_gauge_common(dp_ctx* c, const double2* Udev, hipStream_t st) {
   DP_TRY(drop_masses(c));
+  c->sf = false;
+  c->ct_tilde = 1.0;
   const Geom& g = c->g;
   for (int prec = 0; prec < 3; ++prec) {
     for (int p = 0; p < 2; ++p) DP_HIP(c, c->U[prec][p].reserve((size_t)g.Vp * link_site_bytes(prec)));
@@ -514,6 +516,37 @@ int set_gauge_common(dp_ctx* c, const double2* Udev, hipStream_t st) {
   c->clover_kind = 0;
   c->csw = 0.0;
   return clover_zero(c);
+}
+
+// Schroedinger functional: the clover term of the interior built on the
+// padded lattice (the boundary links in its first and last timeslices), plus
+// (ct_tilde - 1) on the diagonal next to the boundaries; csw = 0 gives the
+// counterterm alone.
+int clover_sf(dp_ctx* c, double csw) {
+  const Geom& g = c->g;
+  Geom gp = g;
+  gp.T = g.T + 2;
+  gp.Vh = gp.T * gp.Vsh;
+  gp.Vp = gp.Vh;
+  DevBuf Up[2], Cp[2];
+  for (int p = 0; p < 2; ++p) {
+    DP_HIP(c, Up[p].reserve((size_t)gp.Vp * link_site_bytes(F64)));
+    DP_HIP(c, Cp[p].reserve((size_t)gp.Vp * clover_site_bytes(F64)));
+  }
+  void* up[2] = {Up[0].p, Up[1].p};
+  DP_HIP(c, launch_gauge_reorder(gp, c->sf_ext.as<double2>(), up, F64, c->stream));
+  double2* cp[2] = {Cp[0].as<double2>(), Cp[1].as<double2>()};
+  if (csw != 0.0) {
+    const double2* u64[2] = {Up[0].as<double2>(), Up[1].as<double2>()};
+    DP_HIP(c, launch_clover_build(gp, u64, csw, cp, c->stream));
+  } else {
+    for (int p = 0; p < 2; ++p) DP_HIP(c, hipMemsetAsync(Cp[p].p, 0, Cp[p].bytes, c->stream));
+  }
+  const double2* cpc[2] = {cp[0], cp[1]};
+  double2* C[2] = {c->C64[0].as<double2>(), c->C64[1].as<double2>()};
+  DP_HIP(c, launch_clover_sf_interior(g, gp, cpc, c->ct_tilde - 1.0, C, c->stream));
+  DP_HIP(c, hipStreamSynchronize(c->stream));  // the temporaries are freed on return
+  return DP_OK;
 }
 
 }  // namespace
@@ -609,12 +642,48 @@ int dp_set_gauge_dev(dp_ctx* c, const void* U, void* stream) {
   return set_gauge_common(c, static_cast<const double2*>(U), c->stream);
 }
 
+int dp_set_gauge_sf(dp_ctx* c, const double* U_ext, double ct_tilde) {
+  if (!c || !U_ext || !std::isfinite(ct_tilde)) return fail(c, DP_ERR_INVALID_ARG, "bad argument");
+  if (c->bc_t != 0) return fail(c, DP_ERR_BAD_STATE, "the Schroedinger functional needs a ctx with bc_t = 0");
+  DP_HIP(c, hipSetDevice(c->device));
+  const Geom& g = c->g;
+  const size_t per_t = (size_t)2 * g.Vsh * 4 * 9;  // double2 per timeslice
+  DP_HIP(c, c->sf_ext.reserve(sizeof(double2) * per_t * (g.T + 2)));
+  DP_HIP(c, hipMemcpyAsync(c->sf_ext.p, U_ext, sizeof(double2) * per_t * (g.T + 2), hipMemcpyHostToDevice,
+                           c->stream));
+  // the interior links, as dp_set_gauge (which clears the SF state: set it after)
+  DP_TRY(set_gauge_common(c, c->sf_ext.as<double2>() + per_t, c->stream));
+  c->sf = true;
+  c->ct_tilde = ct_tilde;
+  // the counterterm applies from now on (with c_sw = 0 until dp_set_clover)
+  DP_TRY(clover_sf(c, 0.0));
+  DP_TRY(clover_convert_all(c));
+  DP_HIP(c, hipStreamSynchronize(c->stream));
+  c->clover_kind = ct_tilde != 1.0 ? 1 : 0;
+  return DP_OK;
+}
+
+int dp_sf_wall_sources(dp_ctx* c, int c0, int ncols, void* eta, void* stream) {
+  if (!c || !eta) return fail(c, DP_ERR_INVALID_ARG, "null argument");
+  if (c0 < 0 || ncols < 1 || c0 + ncols > 12) return fail(c, DP_ERR_INVALID_ARG, "need 0 <= c0 and c0 + ncols <= 12");
+  if (!c->sf) return fail(c, DP_ERR_BAD_STATE, "no Schroedinger-functional links set (dp_set_gauge_sf)");
+  DP_HIP(c, hipSetDevice(c->device));
+  if (stream) DP_HIP(c, hipStreamSynchronize((hipStream_t)stream));
+  DP_HIP(c, launch_sf_wall_sources(c->g, c->sf_ext.as<double2>(), c0, ncols, static_cast<double2*>(eta), c->stream));
+  DP_HIP(c, hipStreamSynchronize(c->stream));
+  return DP_OK;
+}
+
 int dp_set_clover(dp_ctx* c, double csw) {
   if (!c || !std::isfinite(csw)) return fail(c, DP_ERR_INVALID_ARG, "bad argument");
   DP_HIP(c, hipSetDevice(c->device));
   DP_TRY(check_state(c));
   DP_TRY(drop_masses(c));
-  if (csw == 0.0) {
+  if (c->sf) {
+    DP_TRY(clover_sf(c, csw));
+    DP_TRY(clover_convert_all(c));
+    c->clover_kind = 1;
+  } else if (csw == 0.0) {
     DP_TRY(clover_zero(c));
     c->clover_kind = 0;
   } else {

@@ -31,6 +31,8 @@ from .fields import (  # noqa: F401
     point_sources_12,
     gauge_transform,
     volume,
+    sf_boundary_link,
+    gauge_su3_sf,
 )
 from .profiles import alpha_exp, alpha_exp_sym, alpha_cosh_paper, alpha_table, beta_cosh_paper  # noqa: F401
 from .configs import CONFIGS, config  # noqa: F401

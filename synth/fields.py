@@ -106,3 +106,26 @@ def point_sources_12(dims, site, ncols=12):
     for c in range(ncols):
         eta[(c,) + tuple(site) + (c // 3, c % 3)] = 1.0
     return eta
+
+
+def sf_boundary_link(phi, L):
+    """An abelian boundary link of the Schroedinger functional:
+    diag(exp(i phi_a / L)), phi a triple summing to zero (SU(3))."""
+    phi = np.asarray(phi, dtype=np.float64)
+    return np.diag(np.exp(1j * phi / L))
+
+
+def gauge_su3_sf(dims, eps, seed, phi=(0.0, 0.0, 0.0), phi_prime=(0.0, 0.0, 0.0), interior_free=False):
+    """Links of a Schroedinger-functional lattice whose interior has
+    dims = (T, L1, L2, L3): an array of T + 2 timeslices (index 0 the boundary
+    x0 = 0, T + 1 the boundary x0 = T + 1).  All links are drawn as in
+    gauge_su3 (or are unit links with interior_free), then the spatial links of
+    the two boundary timeslices are set to the constant abelian fields of phi
+    and phi_prime (direction k: diag(exp(i phi_a / L_k)))."""
+    T, L1, L2, L3 = dims
+    ext = (T + 2, L1, L2, L3)
+    U = free_gauge(ext) if interior_free else gauge_su3(ext, eps, seed)
+    for k, L in enumerate((L1, L2, L3), start=1):
+        U[0, :, :, :, k] = sf_boundary_link(phi, L)
+        U[T + 1, :, :, :, k] = sf_boundary_link(phi_prime, L)
+    return U
