@@ -20,6 +20,10 @@ HIPCC_FLAGS = [
     "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fused multiply-adds only within one source expression: the rounding of
+    # a computation is fixed by the source, not by the kernel it is inlined
+    # into (the one-slot and the shared-tile hop kernels then agree bitwise)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

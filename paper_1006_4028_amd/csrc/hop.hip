@@ -190,15 +190,18 @@ constexpr int shared_pf() {
   return P == F16 ? DP_SHARED_PF16 : P == F32 ? DP_SHARED_PF32 : 2;
 }
 
-// The slab kernel can run the same batched code with the links read from
-// memory (prefetched with the spinors); off by default (DP_SLAB_PF32 = 0:
-// the per-direction code).
+// The one-slot FP32 slab kernel runs the same batched code with the links
+// read from memory, prefetched with the spinors (measured on MI355X at
+// 24^3x48: 3% faster than the per-direction code); FP16 keeps the latter.
 #ifndef DP_SLAB_PF32
-#define DP_SLAB_PF32 0
+#define DP_SLAB_PF32 4
+#endif
+#ifndef DP_SLAB_PF16
+#define DP_SLAB_PF16 0
 #endif
 template <int P>
 constexpr int slab_pf() {
-  return P == F32 ? DP_SLAB_PF32 : 0;
+  return P == F32 ? DP_SLAB_PF32 : P == F16 ? DP_SLAB_PF16 : 0;
 }
 
 template <int P>
@@ -283,6 +286,7 @@ template <int P, int K0, int PF, bool DAG, bool LDSL>
 __device__ __forceinline__ void nb_batches(const HopArgs& a, int slot, int i, const int (&nb)[8],
                                            const typename Tr<P>::R (&coef)[8], const cx<typename Tr<P>::R>* lu,
                                            int lane, cx<typename Tr<P>::R> (&acc)[12]) {
+  static_assert(PF > 0 && 8 % PF == 0, "the batches must split the 8 neighbours evenly");
   if constexpr (K0 < 8) {
     RawSpinor<P> raw[PF];
     RawLink<P> rl[PF];  // unused (and eliminated) with LDS links
@@ -306,6 +310,27 @@ __device__ __forceinline__ void nb_batches(const HopArgs& a, int slot, int i, co
 // With LDS the clover blocks come from the workgroup's copy lc[72][64] of the
 // stored values times the FP16 per-site scale (the same product the direct
 // load forms, so the block is bitwise the same).
+// Whether the shared-tile kernel stages the clover blocks of the even-site
+// epilogue in LDS (else each wave reads them from memory, through L2).
+#ifndef DP_SHARED_CLOVER32
+#define DP_SHARED_CLOVER32 1
+#endif
+template <int P, int EPI>
+constexpr bool shared_clover() {
+  return EPI == EPI_DIAG && (P != F32 || DP_SHARED_CLOVER32);
+}
+
+// Chirality block h of the workgroup's LDS copy lc[72][64] (values in the
+// order of the stored blocks: 6 diagonal reals, then 15 complex entries).
+template <typename R>
+__device__ __forceinline__ void lds_block(const float* lc, int h, int lane, HermBlock<R>& B) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) B.d[k] = (R)lc[(36 * h + k) * 64 + lane];
+#pragma unroll
+  for (int k = 0; k < 15; ++k)
+    B.o[k] = cx<R>{(R)lc[(36 * h + 6 + 2 * k) * 64 + lane], (R)lc[(36 * h + 7 + 2 * k) * 64 + lane]};
+}
+
 template <int P, int EPI, int RED, bool NT, bool LDS, bool LINV>
 __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<typename Tr<P>::R> (&acc)[12],
                                          double (&red)[kRedMax], const float* lc, int lane) {
@@ -319,18 +344,22 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
 #pragma unroll
     for (int c = 0; c < 12; ++c) out[c] = R(-0.5) * acc[c];
   } else if constexpr (EPI == EPI_DIAG) {
-    HermBlock<R> B[2];
-    if constexpr (LDS) {
-      float r[72];
-#pragma unroll
-      for (int k = 0; k < 72; ++k) r[k] = lc[k * 64 + lane];
-      CloverIO<F32>::assemble(r, 1.f, B);  // the values are already scaled
-    } else {
-      CloverIO<P>::load(a.clov.data, a.clov.scale, i, g.Vp, B);
-    }
     const R m4 = (R)a.slots.m4[slot];
-    herm_apply(B[0], m4, &xin[0], &out[0]);
-    herm_apply(B[1], m4, &xin[6], &out[6]);
+    if constexpr (LDS && shared_clover<P, EPI>()) {
+      // one chirality block at a time (fewer live registers); the values
+      // are already scaled
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        HermBlock<R> Bh;
+        lds_block(lc, h, lane, Bh);
+        herm_apply(Bh, m4, &xin[6 * h], &out[6 * h]);
+      }
+    } else {
+      HermBlock<R> B[2];
+      CloverIO<P>::load(a.clov.data, a.clov.scale, i, g.Vp, B);
+      herm_apply(B[0], m4, &xin[0], &out[0]);
+      herm_apply(B[1], m4, &xin[6], &out[6]);
+    }
     const R hs = (R)(-0.5 * a.sign);
 #pragma unroll
     for (int c = 0; c < 12; ++c) out[c] = out[c] + hs * acc[c];
@@ -346,18 +375,20 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int slot, int i, cx<t
 #pragma unroll
       for (int c = 0; c < 12; ++c) t[c] = R(-0.5) * acc[c];
     }
-    HermBlock<R> B[2];
     if constexpr (LDS && LINV) {  // every slot's A^-1 is the workgroup's copy (scaled)
-      float r[72];
 #pragma unroll
-      for (int k = 0; k < 72; ++k) r[k] = lc[k * 64 + lane];
-      CloverIO<F32>::assemble(r, 1.f, B);
+      for (int h = 0; h < 2; ++h) {
+        HermBlock<R> Bh;
+        lds_block(lc, h, lane, Bh);
+        herm_apply(Bh, R(0), &t[6 * h], &out[6 * h]);
+      }
     } else {
+      HermBlock<R> B[2];
       const float* sc = a.slots.ainv_scale ? a.slots.ainv_scale[slot] : nullptr;
       CloverIO<P>::load(a.slots.ainv[slot], sc, i, g.Vp, B);
+      herm_apply(B[0], R(0), &t[0], &out[0]);
+      herm_apply(B[1], R(0), &t[6], &out[6]);
     }
-    herm_apply(B[0], R(0), &t[0], &out[0]);
-    herm_apply(B[1], R(0), &t[6], &out[6]);
   }
   SpinorIO<P>::template store<NT>(a.out, slot, i, g.Vp, out);
   if constexpr (RED == RED_DOT_EXT || RED == RED_TS4)
@@ -567,12 +598,14 @@ constexpr size_t shared_tile_bytes(bool clover) {
   return 8 * 9 * 64 * sizeof(cx<R>) + (clover ? 72 * 64 * sizeof(float) : 0);
 }
 
-// Workgroups of up to 12 waves (at most 168 registers per lane, three waves
-// per SIMD), 8 for the fused reduction with the shadow residual (~200); each
-// wave takes slot groups wv, wv + nw, ...  FP16 storage needs more registers
-// for its neighbour loads (at three waves per SIMD the compiler spills): its
-// workgroups have 4 waves with two waves per SIMD (256 registers), two
-// workgroups per CU.
+// Workgroups of 4 waves at two waves per SIMD (up to 256 registers per lane:
+// the batched neighbour loads hold four spinors and links in flight), two
+// workgroups per CU (the LDS tile takes 55 KB); each wave takes slot groups
+// wv, wv + nw, ...  Measured on MI355X at 24^3x48 with 12 slots (FP32): three
+// waves per SIMD (two batched neighbours, at most 168 registers) in 12-, 6-
+// or 4-wave workgroups, one workgroup per CU, or eight neighbours in flight
+// were all 1-35% slower.  The build knobs DP_SHARED_WG32 / DP_SHARED_MINW32
+// set the FP32 workgroup size bound and the waves per SIMD.
 #ifndef DP_SHARED_WG32
 #define DP_SHARED_WG32 256
 #endif
@@ -584,7 +617,7 @@ constexpr int shared_max_threads(int red) {
   return P == F16 ? 256 : red == RED_TS4 ? 512 : DP_SHARED_WG32;
 }
 template <int P>
-constexpr int shared_min_waves() { return P == F16 ? 2 : DP_SHARED_MINW32; }
+constexpr int shared_min_waves(int red) { return P == F16 || red == RED_TS4 ? 2 : DP_SHARED_MINW32; }
 
 // The staged links and blocks are read once per launch: streamed past L2
 // (measured on MI355X at 24^3x48 with 12 slots: 2-3% faster).
@@ -592,7 +625,7 @@ constexpr bool kFillNT = true;
 
 // LINV: the odd-site epilogue's A^-1, the same for every slot, is staged too.
 template <int P, int EPI, int RED, int NS, bool NT, bool DAG, bool LINV>
-__global__ void __launch_bounds__(shared_max_threads<P>(RED), shared_min_waves<P>()) hop_kernel_shared(HopArgs a,
+__global__ void __launch_bounds__(shared_max_threads<P>(RED), shared_min_waves<P>(RED)) hop_kernel_shared(HopArgs a,
                                                                                                    SlabMap m) {
   using R = typename Tr<P>::R;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -616,7 +649,7 @@ __global__ void __launch_bounds__(shared_max_threads<P>(RED), shared_min_waves<P
   // fill: tasks 0..7 are the link directions (2 mu forward, 2 mu + 1 backward),
   // task 8 the clover blocks (even-site epilogue) or the A^-1 blocks all
   // slots share (odd-site epilogues); wave w takes tasks w, w + nw, ...
-  constexpr bool blocks = EPI == EPI_DIAG || LINV;
+  constexpr bool blocks = shared_clover<P, EPI>() || LINV;
   if (valid) {
     int x[4];
     eo_coords(g, a.p, i, x[0], x[1], x[2], x[3]);
@@ -707,33 +740,29 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
     // tuning knob: DP_HOP_LDS = bytes of (unused) LDS per block, which caps the
     // blocks resident per CU (160 KB of LDS per CU) and so the sweep front
     static const int lds = std::min(65536, std::max(0, env_knob("DP_HOP_LDS", 0)));
-    // FP32 with two or more slots: the shared-tile kernel, one slot per wave
-    // (measured on MI355X at 24^3x48 with 12 slots: 16% faster than the slab
-    // kernel with two slots per thread; in FP16 it was slower, the compiler
-    // then takes 250 registers per lane).  Tuning knob: DP_HOP_SHARED = 0
-    // keeps one workgroup per slot group.
+    // Two or more slots in FP32 or FP16: the shared-tile kernel, one slot per
+    // wave (measured on MI355X at 24^3x48 with 12 slots: FP32 16% faster
+    // than the slab kernel with two slots per thread, FP16 12% faster on the
+    // even sites).  Not for the FP16 kernels with the four-term reduction or
+    // the reconstruction epilogue: at the shared-tile kernel's two waves per
+    // SIMD they spill.  One slot: the slab kernel (a one-wave shared-tile
+    // workgroup holds as much LDS as a full one, and the CUs would run one
+    // wave each).  The library is built with contraction limited to single
+    // expressions, so both kernels round alike and a slot's results are
+    // bitwise the same alone and in any batch.  Tuning knob: DP_HOP_SHARED
+    // = 0 keeps one workgroup per slot group.
     static const bool shared = env_knob("DP_HOP_SHARED", 1) == 1;
-    // FP16 storage keeps the slab kernel: through the shared-tile kernel
-    // (links and scaled clover values converted to FP32 once in LDS, 4-wave
-    // workgroups at two waves per SIMD) it was measured on MI355X at 24^3x48
-    // with 12 slots 8-14% faster, but with the fixed fused-multiply-add
-    // arithmetic it needs more than 256 registers and spills.
-    // FP32 runs the shared-tile kernel for any number of slots, one slot
-    // alone included: a slot's arithmetic is then the same code whatever the
-    // batch it is in, so its results are bitwise the same alone and in any
-    // mix (with a single slot the workgroup is one wave).
-    if constexpr (P == F32) {
-      if (shared && nt && !forced) {
+    constexpr bool shared_ok = P == F32 || (P == F16 && RED != RED_TS4 && EPI != EPI_INV_SUB);
+    if constexpr (shared_ok) {
+      if (shared && nt && !forced && a.nslots >= 2) {
         m.ngroups = a.nslots;
-        // waves per workgroup: the fewest passes of at most 12 waves, one
-        // 12-wave workgroup per CU (three waves per SIMD): half as many
-        // workgroups in flight per XCD as with two 6-wave ones, so the sweep
-        // front spans fewer timeslices and more of the x0 neighbours stay in
-        // L2 (measured on MI355X at 24^3x48 with 12 slots: 5% faster).  The
-        // RED_TS4 kernel takes ~200 registers (two waves per SIMD) and runs
-        // 4-wave workgroups (3% faster per solve than 6).  Tuning knobs:
-        // DP_HOP_MAXW, DP_HOP_TS4_WAVES.
+        // waves per workgroup: the fewest passes of at most the bound's
+        // waves (four by default; the RED_TS4 kernel four of its eight).
+        // Tuning knobs: DP_HOP_MAXW, DP_HOP_TS4_WAVES.
         static const int maxw_ts4 = std::min(8, std::max(1, env_knob("DP_HOP_TS4_WAVES", 4)));
+        // tuning knob: DP_HOP_SHARED_LDS = bytes of (unused) LDS added per
+        // workgroup, which caps the workgroups resident per CU
+        static const int lds_extra = std::min(65536, std::max(0, env_knob("DP_HOP_SHARED_LDS", 0)));
         static const int maxw_other =
             std::min(shared_max_threads<P>(RED) / 64, std::max(1, env_knob("DP_HOP_MAXW", 12)));
         const int maxw = P == F16 ? shared_max_threads<P>(RED) / 64 : RED == RED_TS4 ? maxw_ts4 : maxw_other;
@@ -742,10 +771,10 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
         constexpr bool inv = EPI == EPI_INV || EPI == EPI_INV_SUB;
         if (inv && a.slots.ainv_common)
           hipLaunchKernelGGL((hop_kernel_shared<P, EPI, RED, 1, true, DAG, inv>), sgrid, sblock,
-                             shared_tile_bytes<P>(true), st, a, m);
+                             shared_tile_bytes<P>(true) + lds_extra, st, a, m);
         else
           hipLaunchKernelGGL((hop_kernel_shared<P, EPI, RED, 1, true, DAG, false>), sgrid, sblock,
-                             shared_tile_bytes<P>(EPI == EPI_DIAG), st, a, m);
+                             shared_tile_bytes<P>(shared_clover<P, EPI>()) + lds_extra, st, a, m);
         *nparts_out = nparts;
         return hipGetLastError();
       }
