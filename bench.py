@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Dslash HBM GB/s (% roofline); solves/s + p99 latency, mixed vs FP64 at r=1e-11"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hop_f32_diag_24c48_12rhs.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hop_kernels_24c48_12rhs.json")
 KERNEL_SOURCES = ["paper_1006_4028_amd/csrc/hop.hip", "paper_1006_4028_amd/csrc/dp_device.h",
                   "paper_1006_4028_amd/csrc/dp_common.h"]
 
@@ -45,9 +45,9 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    record, if it was taken on the current kernel sources (else None)."""
+def measured_traffic(kernel="hop_f32_diag"):
+    """HBM bytes per full launch of a hop kernel class from the committed
+    counter record, if it was taken on the current kernel sources (else None)."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -55,12 +55,16 @@ def measured_traffic():
         return None
     if rec.get("source_sha256") != kernel_source_hash():
         return None
-    return rec["hbm_bytes_per_launch"]
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["hbm_bytes_per_launch"]
 
 
 def pmc_probe():
     """Run under rocprofv3 --pmc: a 1 GiB device copy (the counters' scale),
-    then one step of the timed configuration (12 columns, FP32 inner)."""
+    then one solve of the timed configuration (12 columns) with FP32 and one
+    with FP16 inner precision, with per-kernel timing on (graphs off), and
+    print the algorithmic bytes per launch of each hop kernel class as one
+    JSON line."""
     import torch
     x = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
@@ -79,16 +83,36 @@ def pmc_probe():
     L.set_clover(cfg["csw"])
     L.set_mass(cfg["masses"][0])
     L.set_alpha(synth.alpha_table(cfg["profile"], dims[0], cfg["alpha0s"][-1]))
-    L.solve_dev(e_t, None, r=cfg["r"], precision="f32", ncols_group=12)
-    torch.cuda.synchronize()
+    alg = {}
+    for prec in ("f32", "f16"):
+        L.set_timing(True)
+        L.solve_dev(e_t, None, r=cfg["r"], precision=prec, ncols_group=12)
+        torch.cuda.synchronize()
+        for name, st in L.timing().items():
+            if name.startswith("hop_") and st["launches"]:
+                alg[name] = max(alg.get(name, 0.0), st["bytes"] / st["launches"])
+        L.set_timing(False)
     L.close()
+    print(json.dumps({"alg_bytes_per_launch": alg}), flush=True)
 
 
-def pmc_summary(fetch_csv, write_csv, command):
-    """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the dominant kernel
-    (the FP32 even-site hop with the clover epilogue, full 12-slot launches) by
-    what the same counters read for the 1 GiB copy, and record them."""
+# counter-record kernel classes: (timer name, test on the kernel's template
+# arguments <precision, epilogue, ...>)
+PMC_CLASSES = {
+    "hop_f32_diag": lambda a: a[0] == 1 and a[1] == 2,
+    "hop_f32_inv": lambda a: a[0] == 1 and a[1] in (1, 4),
+    "hop_f16_diag": lambda a: a[0] == 2 and a[1] == 2,
+    "hop_f16_inv": lambda a: a[0] == 2 and a[1] in (1, 4),
+}
+
+
+def pmc_summary(fetch_csv, write_csv, alg_json, command):
+    """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the 12-slot hop
+    kernels by what the same counters read for the 1 GiB copy, average them
+    over the full launches of each kernel class (every slot active) and
+    record them with the algorithmic bytes of the same launches."""
     import csv
+    import re
 
     def rows(path):
         return list(csv.DictReader(open(path)))
@@ -96,23 +120,35 @@ def pmc_summary(fetch_csv, write_csv, command):
     def is_copy(r):
         return "copyBuffer" in r["Kernel_Name"] or "copy" in r["Kernel_Name"].lower() and "dp::" not in r["Kernel_Name"]
 
-    def is_hop(r):
-        return "hop_kernel" in r["Kernel_Name"] and "<1, 2, 1," in r["Kernel_Name"] or \
-            "hop_kernel" in r["Kernel_Name"] and "<1, 2, 4," in r["Kernel_Name"]
+    def targs(r):
+        m = re.search(r"hop_kernel_(?:shared|slab)<([^>]*)>", r["Kernel_Name"])
+        return None if not m else [int(v) if v.strip().lstrip("-").isdigit() else v.strip() for v in m.group(1).split(",")]
 
-    out = {}
+    line = [x for x in open(alg_json).read().splitlines() if '"alg_bytes_per_launch"' in x][-1]
+    alg = json.loads(line)["alg_bytes_per_launch"]
+    scale, per = {}, {}
     for key, path in (("fetch", fetch_csv), ("write", write_csv)):
         rs = rows(path)
         copy = max(float(r["Counter_Value"]) for r in rs if is_copy(r))
-        hop = [float(r["Counter_Value"]) for r in rs if is_hop(r)]
-        full = [v for v in hop if v > 0.5 * max(hop)]  # launches with every slot active
-        out[key + "_kib_per_launch"] = sum(full) / len(full)
-        out[key + "_copy_kib"] = copy
-        out[key + "_scale"] = (1 << 20) / copy  # 1 GiB = 2^20 KiB moved by the copy
-        out[key + "_launches"] = len(full)
-    hbm = 1024 * (out["fetch_kib_per_launch"] * out["fetch_scale"] + out["write_kib_per_launch"] * out["write_scale"])
-    rec = {"kernel": "hop_f32_diag (hop_kernel_shared<1, 2, 1|4, 1>), 24^3x48, 12 slots", "command": command,
-           "source_sha256": kernel_source_hash(), "hbm_bytes_per_launch": hbm, **out}
+        scale[key] = {"copy_kib": copy, "scale": (1 << 20) / copy}  # the copy moves 1 GiB = 2^20 KiB
+        for cls, test in PMC_CLASSES.items():
+            vals = [float(r["Counter_Value"]) for r in rs if targs(r) and test(targs(r))]
+            if not vals:
+                continue
+            full = [v for v in vals if v > 0.5 * max(vals)]
+            per.setdefault(cls, {})[key] = (sum(full) / len(full), len(full))
+    kernels = {}
+    for cls, d in per.items():
+        if "fetch" not in d or "write" not in d:
+            continue
+        hbm = 1024 * (d["fetch"][0] * scale["fetch"]["scale"] + d["write"][0] * scale["write"]["scale"])
+        a = alg.get(cls)
+        kernels[cls] = {"hbm_bytes_per_launch": hbm, "fetch_kib_per_launch": d["fetch"][0],
+                        "write_kib_per_launch": d["write"][0], "launches": d["fetch"][1],
+                        "alg_bytes_per_launch": a, "traffic_over_alg": None if not a else round(hbm / a, 3)}
+    rec = {"workload": "24^3x48, 12 slots, one FP32-inner and one FP16-inner solve to r=1e-11",
+           "command": command, "source_sha256": kernel_source_hash(),
+           "fetch_scale": scale["fetch"], "write_scale": scale["write"], "kernels": kernels}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec, indent=1))
@@ -157,7 +193,7 @@ def main():
     ap.add_argument("--sap-study", action="store_true",
                     help="SAP+GCR iteration counts vs alpha0 of the light-quark factorisation (one JSON line)")
     ap.add_argument("--pmc-probe", action="store_true", help="run the counter probe (under rocprofv3 --pmc)")
-    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "ALG_JSON", "COMMAND"),
                     help="write the traffic record of the dominant kernel from two counter runs")
     args = ap.parse_args()
     if args.pmc_probe:
@@ -339,6 +375,7 @@ def main():
         "speedup_vs_fp64": round(solves_per_s / fp64["value"], 3) if fp64 else None,
         "roofline": {"bound": "hbm", "kernel": name, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_over_alg": round(traffic / (st["bytes"] / st["launches"]), 3) if traffic else None,
                      "avg_launch_us": round(1e3 * avg_ms, 2),
                      "alg_bytes_per_launch": st["bytes"] / st["launches"],
                      "all_hop_kernels_GBps": round(all_hop_gbs, 1),

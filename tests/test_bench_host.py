@@ -30,25 +30,35 @@ def test_counter_summary_scales_by_the_copy(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
     hop = "void dp::(anonymous namespace)::hop_kernel_shared<1, 2, 1, 1, true, false, false>(dp::HopArgs, x)"
     hop4 = "void dp::(anonymous namespace)::hop_kernel_shared<1, 2, 4, 1, true, false, false>(dp::HopArgs, x)"
-    other = "void dp::(anonymous namespace)::hop_kernel_shared<1, 1, 0, 1, true, false, true>(dp::HopArgs, x)"
+    inv = "void dp::(anonymous namespace)::hop_kernel_shared<1, 1, 0, 1, true, false, true>(dp::HopArgs, x)"
+    h16 = "void dp::(anonymous namespace)::hop_kernel_slab<2, 2, 4, 1, true, false>(dp::HopArgs, x)"
     # the 1 GiB copy reads as half its size in FETCH_SIZE and exactly in WRITE_SIZE;
-    # a launch with few active slots (the last one) is left out of the mean
+    # a launch with few active slots (the last hop one) is left out of the mean
     _csv(tmp_path / "f.csv", [("__amd_rocclr_copyBuffer", 524288), (hop, 1000.0), (hop4, 1200.0), (hop, 100.0),
-                              (other, 5000.0)])
+                              (inv, 5000.0), (h16, 700.0)])
     _csv(tmp_path / "w.csv", [("__amd_rocclr_copyBuffer", 1048576), (hop, 300.0), (hop4, 300.0), (hop, 30.0),
-                              (other, 900.0)])
-    bench.pmc_summary(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), "cmd")
+                              (inv, 900.0), (h16, 200.0)])
+    (tmp_path / "alg.json").write_text(json.dumps({"alg_bytes_per_launch": {"hop_f32_diag": 1024 * 2000.0}}))
+    bench.pmc_summary(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(tmp_path / "alg.json"), "cmd")
     rec = json.load(open(tmp_path / "traffic.json"))
-    assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
-    assert rec["fetch_launches"] == 2 and rec["write_launches"] == 2
-    assert rec["hbm_bytes_per_launch"] == 1024 * (1100.0 * 2.0 + 300.0)
+    assert rec["fetch_scale"]["scale"] == 2.0 and rec["write_scale"]["scale"] == 1.0
+    k = rec["kernels"]
+    assert set(k) == {"hop_f32_diag", "hop_f32_inv", "hop_f16_diag"}
+    assert k["hop_f32_diag"]["launches"] == 2
+    assert k["hop_f32_diag"]["hbm_bytes_per_launch"] == 1024 * (1100.0 * 2.0 + 300.0)
+    assert k["hop_f32_diag"]["traffic_over_alg"] == round((1100.0 * 2.0 + 300.0) / 2000.0, 3)
+    assert k["hop_f32_inv"]["hbm_bytes_per_launch"] == 1024 * (5000.0 * 2.0 + 900.0)
+    assert k["hop_f32_inv"]["traffic_over_alg"] is None
+    assert k["hop_f16_diag"]["hbm_bytes_per_launch"] == 1024 * (700.0 * 2.0 + 200.0)
     assert rec["source_sha256"] == bench.kernel_source_hash()
 
 
 def test_counter_record_of_other_sources_is_ignored(tmp_path, monkeypatch):
     path = tmp_path / "traffic.json"
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
-    json.dump({"source_sha256": "0" * 64, "hbm_bytes_per_launch": 1.0}, open(path, "w"))
+    rec = {"kernels": {"hop_f32_diag": {"hbm_bytes_per_launch": 2.5}}}
+    json.dump({"source_sha256": "0" * 64, **rec}, open(path, "w"))
     assert bench.measured_traffic() is None
-    json.dump({"source_sha256": bench.kernel_source_hash(), "hbm_bytes_per_launch": 2.5}, open(path, "w"))
+    json.dump({"source_sha256": bench.kernel_source_hash(), **rec}, open(path, "w"))
     assert bench.measured_traffic() == 2.5
+    assert bench.measured_traffic("hop_f16_inv") is None
