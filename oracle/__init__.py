@@ -36,7 +36,8 @@ class OracleError(RuntimeError):
 def _lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "liborc.so")
+        # ORC_LIB names another build of orc.c (the sanitizer test uses it)
+        path = os.environ.get("ORC_LIB") or os.path.join(_HERE, "liborc.so")
         if not os.path.exists(path):
             from .build import build
             build()

@@ -18,5 +18,17 @@ def build(verbose=False):
     return out
 
 
+def build_sanitized(out, verbose=False):
+    """The same library with AddressSanitizer and UndefinedBehaviorSanitizer
+    (host code; any report aborts), for the sanitizer test."""
+    src = os.path.join(_HERE, "orc.c")
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", src, "-o", out, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
