@@ -546,9 +546,32 @@ __global__ void __launch_bounds__(kBlock) hop_kernel(HopArgs a) {
 // (about 3 timeslices of its slab).  Block b runs on XCD b mod 8.
 struct SlabMap {
   int nch, maxc, ngroups, order;
+  int tmap, tlen;  // time mapping (see time_item) and the longest XCD time range
 };
 
 __device__ __forceinline__ int slab_lo(int nch, int xcd) { return (nch * xcd) >> 3; }
+
+// Time mapping (tmap = 1): XCD k owns the timeslices [T k / 8, T (k+1) / 8)
+// of every chunk instead of a spatial slab of every timeslice, and takes
+// its (chunk, timeslice) items chunk by chunk, the timeslices innermost.
+// Block j of an XCD (after the slot groups, slab kernel) is timeslice
+// j mod tlen of its range and chunk j / tlen; blocks past the range or the
+// last chunk own nothing.  The reduction partial of an item is x0 nch +
+// chunk (nparts = T nch), the same in both kernels.
+struct Item {
+  int chunk, x0, part;
+  bool in;
+};
+__device__ __forceinline__ Item time_item(const SlabMap& m, int T, int xcd, int j, bool backwards) {
+  Item it;
+  const int lo = (T * xcd) >> 3, hi = (T * (xcd + 1)) >> 3;
+  const int dt = j % m.tlen;
+  it.chunk = j / m.tlen;
+  it.in = lo + dt < hi && it.chunk < m.nch;
+  it.x0 = backwards ? hi - 1 - dt : lo + dt;
+  it.part = it.x0 * m.nch + it.chunk;
+  return it;
+}
 
 // No minimum-waves hint: measured on MI355X at 24^3x48 with 12 slots, asking
 // for 3 waves per SIMD in FP32 (two slots per thread) or 4 in FP16 makes the
@@ -557,6 +580,15 @@ template <int P, int EPI, int RED, int NS, bool NT, bool DAG>
 __global__ void __launch_bounds__(64) hop_kernel_slab(HopArgs a, SlabMap m) {
   const int xcd = blockIdx.x & 7;
   int j = blockIdx.x >> 3;
+  if (m.tmap) {
+    const int grp = j % m.ngroups;
+    const Item it = time_item(m, a.g.T, xcd, j / m.ngroups, EPI == EPI_DIAG);
+    if (!it.in) return;  // owns no partial
+    const int sp = it.chunk * 64 + threadIdx.x;
+    const bool valid = sp < a.g.Vsh;
+    site_work<P, EPI, RED, NS, NT, DAG>(a, grp, valid ? it.x0 * a.g.Vsh + sp : 0, valid, it.part, a.g.T * m.nch);
+    return;
+  }
   int grp, cl, x0;
   if (m.order == 0) {  // slot groups of a chunk together, then chunks, then timeslices
     grp = j % m.ngroups;
@@ -616,8 +648,13 @@ template <int P>
 constexpr int shared_max_threads(int red) {
   return P == F16 ? 256 : red == RED_TS4 ? 512 : DP_SHARED_WG32;
 }
+#ifndef DP_SHARED_MINW16
+#define DP_SHARED_MINW16 2
+#endif
 template <int P>
-constexpr int shared_min_waves(int red) { return P == F16 || red == RED_TS4 ? 2 : DP_SHARED_MINW32; }
+constexpr int shared_min_waves(int red) {
+  return P == F16 ? DP_SHARED_MINW16 : red == RED_TS4 ? 2 : DP_SHARED_MINW32;
+}
 
 // The staged links and blocks are read once per launch: streamed past L2
 // (measured on MI355X at 24^3x48 with 12 slots: 2-3% faster).
@@ -639,9 +676,24 @@ __global__ void __launch_bounds__(shared_max_threads<P>(RED), shared_min_waves<P
   // timeslices are then still in the caches (measured on MI355X at 24^3x48
   // with 12 slots: 3% faster).  The reduction partials are indexed by x0, so
   // the sums do not depend on the order.
-  const int cl = j % m.maxc, x0 = EPI == EPI_DIAG ? g.T - 1 - j / m.maxc : j / m.maxc;
-  const int chunk = slab_lo(m.nch, xcd) + cl;
-  const bool in_slab = chunk < slab_lo(m.nch, xcd + 1);
+  int chunk, x0, part, nparts;
+  bool in_slab;
+  if (m.tmap) {
+    const Item it = time_item(m, g.T, xcd, j, EPI == EPI_DIAG);
+    if (!it.in) return;  // the whole workgroup owns no partial (before any barrier)
+    chunk = it.chunk;
+    x0 = it.x0;
+    part = it.part;
+    nparts = g.T * m.nch;
+    in_slab = true;
+  } else {
+    const int cl = j % m.maxc;
+    x0 = EPI == EPI_DIAG ? g.T - 1 - j / m.maxc : j / m.maxc;
+    chunk = slab_lo(m.nch, xcd) + cl;
+    in_slab = chunk < slab_lo(m.nch, xcd + 1);
+    part = (xcd * g.T + x0) * m.maxc + cl;
+    nparts = 8 * g.T * m.maxc;
+  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int sp = chunk * 64 + lane;
   const bool valid = in_slab && sp < g.Vsh;
@@ -658,15 +710,15 @@ __global__ void __launch_bounds__(shared_max_threads<P>(RED), shared_min_waves<P
       if (t % nw != wv || (t == 8 && !blocks)) continue;
       if (t < 8) {
         const int mu = t >> 1;  // a constant once unrolled
-        cx<R> u[9];
-        if ((t & 1) == 0) {
-          LinkIO<P>::template load<R, kFillNT>(a.U_out, mu, i, g.Vp, u);
-        } else {
+        int li = i;  // forward hops: the link at the site; backward: at the neighbour
+        if (t & 1) {
           int y[4] = {x[0], x[1], x[2], x[3]};
           const int L = mu == 0 ? g.T : mu == 1 ? g.L1 : mu == 2 ? g.L2 : g.L3;
           y[mu] = x[mu] == 0 ? L - 1 : x[mu] - 1;
-          LinkIO<P>::template load<R, kFillNT>(a.U_in, mu, eo_index(g, y[0], y[1], y[2], y[3]), g.Vp, u);
+          li = eo_index(g, y[0], y[1], y[2], y[3]);
         }
+        cx<R> u[9];
+        LinkIO<P>::template load<R, kFillNT>((t & 1) ? a.U_in : a.U_out, mu, li, g.Vp, u);
 #pragma unroll
         for (int k = 0; k < 9; ++k) lu[(t * 9 + k) * 64 + lane] = u[k];
       } else {
@@ -685,8 +737,7 @@ __global__ void __launch_bounds__(shared_max_threads<P>(RED), shared_min_waves<P
     // keeps the compiler from hoisting the LDS reads out of this loop into
     // (many) registers
     asm volatile("" ::: "memory");
-    site_work<P, EPI, RED, NS, NT, DAG, true, LINV>(a, grp, i, valid, (xcd * g.T + x0) * m.maxc + cl, 8 * g.T * m.maxc,
-                                                    lu, lc, lane);
+    site_work<P, EPI, RED, NS, NT, DAG, true, LINV>(a, grp, i, valid, part, nparts, lu, lc, lane);
   }
 }
 
@@ -735,8 +786,14 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
     // tuning knob: DP_HOP_ORDER in {0, 1, 2} (block order within an XCD)
     static const int order = std::min(2, std::max(0, env_knob("DP_HOP_ORDER", 0)));
     m.order = order;
-    nparts = 8 * a.g.T * m.maxc;
-    const dim3 grid(nparts * ngroups);
+    // tuning knob: DP_HOP_TMAP = 1 gives each XCD a range of timeslices
+    // instead of a spatial slab (time_item)
+    static const int tmap = env_knob("DP_HOP_TMAP", 0) == 1 ? 1 : 0;
+    m.tmap = tmap;
+    m.tlen = (a.g.T + 7) / 8;
+    nparts = tmap ? a.g.T * m.nch : 8 * a.g.T * m.maxc;
+    const int nblocks = tmap ? 8 * m.tlen * m.nch : nparts;  // blocks per slot group
+    const dim3 grid(nblocks * ngroups);
     // tuning knob: DP_HOP_LDS = bytes of (unused) LDS per block, which caps the
     // blocks resident per CU (160 KB of LDS per CU) and so the sweep front
     static const int lds = std::min(65536, std::max(0, env_knob("DP_HOP_LDS", 0)));
@@ -767,7 +824,7 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
             std::min(shared_max_threads<P>(RED) / 64, std::max(1, env_knob("DP_HOP_MAXW", 12)));
         const int maxw = P == F16 ? shared_max_threads<P>(RED) / 64 : RED == RED_TS4 ? maxw_ts4 : maxw_other;
         const int passes = (a.nslots + maxw - 1) / maxw;
-        const dim3 sgrid(nparts), sblock(64 * ((a.nslots + passes - 1) / passes));
+        const dim3 sgrid(nblocks), sblock(64 * ((a.nslots + passes - 1) / passes));
         constexpr bool inv = EPI == EPI_INV || EPI == EPI_INV_SUB;
         if (inv && a.slots.ainv_common)
           hipLaunchKernelGGL((hop_kernel_shared<P, EPI, RED, 1, true, DAG, inv>), sgrid, sblock,
