@@ -140,8 +140,8 @@ int dp_set_gauge_dev(dp_ctx* ctx, const void* U_dev, void* hip_stream);
  * ctx's gauge field (as dp_set_gauge); the spatial links of the two
  * boundaries (the boundary gauge fields) and the time links between them
  * and the interior enter the clover term next to the boundaries, which
- * dp_set_clover builds from the whole lattice; the time links on x0 = 0 give
- * the boundary sources of dp_sf_wall_sources.  ct_tilde is the coefficient
+ * dp_set_clover builds from the whole lattice; the time links into the two
+ * boundaries give the boundary sources of dp_sf_wall_sources.  ct_tilde is the coefficient
  * of the fermion boundary counterterm: (ct_tilde - 1) psi on the first and
  * last interior timeslices (1: none), in force from this call on.  The
  * fermion field vanishes on the boundaries (the hops into them drop).
@@ -150,13 +150,15 @@ int dp_set_gauge_sf(dp_ctx* ctx, const double* U_ext, double ct_tilde);
 
 /* Paper: as dp_set_gauge_sf.
  * The boundary sources of the Schroedinger functional into eta_dev (device,
- * ncols full-lattice spinors, host layout): column j is
- * U_0(x0 = 0, xs)^+ P+ e_c with c = c0 + j (the unit spin-colour vector),
- * P+ = (1 + gamma_0)/2, on the first interior timeslice (every spatial site)
- * and 0 elsewhere: the hop from the boundary field P+ psi(0) = e_c moved to
- * the right-hand side.  Needs dp_set_gauge_sf (else DP_ERR_BAD_STATE) and
+ * ncols full-lattice spinors, host layout), c = c0 + j for column j (e_c the
+ * unit spin-colour vector).  side 0 (boundary x0 = 0): U_0(x0 = 0, xs)^+ P+
+ * e_c on the first interior timeslice, P+ = (1 + gamma_0)/2; side 1
+ * (boundary x0 = T + 1): U_0(x0 = T, xs) P- e_c on the last interior
+ * timeslice, P- = (1 - gamma_0)/2; 0 elsewhere.  Each is the hop from the
+ * boundary field e_c into the interior, moved to the right-hand side.
+ * Needs dp_set_gauge_sf (else DP_ERR_BAD_STATE), side 0 or 1 and
  * 0 <= c0, c0 + ncols <= 12. */
-int dp_sf_wall_sources(dp_ctx* ctx, int c0, int ncols, void* eta_dev, void* hip_stream);
+int dp_sf_wall_sources(dp_ctx* ctx, int side, int c0, int ncols, void* eta_dev, void* hip_stream);
 
 /* Paper: the O(a)-improved Wilson operator named at the start of the
  * heavy-quark section, with the coefficient c_sw of the Table 1 caption.

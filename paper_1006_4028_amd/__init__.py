@@ -82,16 +82,17 @@ class Lattice:
         assert U_ext.size == (self.T + 2) * (self.V // self.T) * 36
         self._check(self._L.dp_set_gauge_sf(self._h, _ptr(U_ext), float(ct_tilde)))
 
-    def sf_wall_sources(self, c0=0, ncols=12, out=None):
-        """The boundary sources U_0(0, xs)^+ P+ e_c on the first interior
-        timeslice, as a complex128 CUDA tensor [ncols, V*12]."""
+    def sf_wall_sources(self, c0=0, ncols=12, out=None, side=0):
+        """The boundary sources of the x0 = 0 boundary (side 0: U_0(0, xs)^+ P+ e_c
+        on the first interior timeslice) or the x0 = T + 1 one (side 1:
+        U_0(T, xs) P- e_c on the last), as a complex128 CUDA tensor [ncols, V*12]."""
         import torch
         if out is None:
             out = torch.empty((ncols, self.V * 12), dtype=torch.complex128, device="cuda")
         assert out.is_cuda and out.is_contiguous() and out.numel() == ncols * self.V * 12
         stream = torch.cuda.current_stream(out.device).cuda_stream
-        self._check(self._L.dp_sf_wall_sources(self._h, int(c0), int(ncols), ctypes.c_void_p(out.data_ptr()),
-                                               ctypes.c_void_p(stream)))
+        self._check(self._L.dp_sf_wall_sources(self._h, int(side), int(c0), int(ncols),
+                                               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
         return out
 
     def set_clover(self, csw):

@@ -99,7 +99,7 @@ def lib():
     L.dp_set_gauge.argtypes = [vp, dp]
     L.dp_set_gauge_dev.argtypes = [vp, vp, vp]
     L.dp_set_gauge_sf.argtypes = [vp, dp, ctypes.c_double]
-    L.dp_sf_wall_sources.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
+    L.dp_sf_wall_sources.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
     L.dp_set_clover.argtypes = [vp, ctypes.c_double]
     L.dp_set_clover_field.argtypes = [vp, dp]
     L.dp_set_mass.argtypes = [vp, ctypes.c_double]

@@ -214,10 +214,12 @@ hipError_t launch_spinor_export(const Geom& g, SpinorRef even, SpinorRef odd, in
 // plus ctm1 on the diagonal of the first and last interior timeslices.
 hipError_t launch_clover_sf_interior(const Geom& g, const Geom& gp, const double2* Cp_eo[2], double ctm1,
                                      double2* C_eo[2], hipStream_t stream);
-// Schroedinger functional boundary sources U_0(0, xs)^+ P+ e_c on the first
-// interior timeslice (U0: the time links on x0 = 0, [xs][mu][3][3] complex).
-hipError_t launch_sf_wall_sources(const Geom& g, const double2* U0, int c0, int ncols, double2* out,
-                                  hipStream_t stream);
+// Schroedinger functional boundary sources: side 0, U_0(0, xs)^+ P+ e_c on
+// the first interior timeslice; side 1, U_0(T, xs) P- e_c on the last (U_t:
+// the links of that boundary-adjacent timeslice of the padded lattice, x0 = 0
+// or x0 = T, host layout [xs][mu][3][3] complex).
+hipError_t launch_sf_wall_sources(const Geom& g, const double2* U_t, int side, int c0, int ncols, double2* out,
+                                  hipStream_t st);
 // ncols unit point sources (host layout, double2 per complex): column j is 1
 // in spin-colour component c0 + j at site {x0, x1, x2, x3}, 0 elsewhere.
 hipError_t launch_point_sources(const Geom& g, const int site[4], int c0, int ncols, double2* out,

@@ -142,26 +142,36 @@ __global__ void __launch_bounds__(kBlock) point_source_kernel(long per_col, long
   }
 }
 
-// The boundary sources of the Schroedinger functional: column j is
-// U_0(x0 = 0, xs)^+ P+ e_c, c = c0 + j, on the first interior timeslice and 0
-// elsewhere, with P+ = (1 + gamma_0)/2 of the chiral basis (the projector the
-// backward time hop applies, so that this is the hop from a boundary field
-// P+ psi(0) = e_c).  U0: the time links on x0 = 0, host layout [xs][mu][3][3].
-__global__ void __launch_bounds__(kBlock) sf_wall_source_kernel(long per_col, long Vs, int c0, int ncols,
-                                                                const double2* __restrict__ U0,
+// The boundary sources of the Schroedinger functional, column j for
+// c = c0 + j: side 0, U_0(x0 = 0, xs)^+ P+ e_c on the first interior
+// timeslice, P+ = (1 + gamma_0)/2 (the projector of the backward time hop,
+// so that this is the hop from a boundary field P+ psi(0) = e_c); side 1,
+// U_0(x0 = T, xs) P- e_c on the last interior timeslice, P- = (1 -
+// gamma_0)/2 (the forward time hop into the boundary field at x0 = T + 1);
+// 0 elsewhere.  In the chiral basis gamma_0 has -1 between spins s and
+// s +- 2, so P+- is 1/2 on the diagonal and -+1/2 between those spins.
+// Ut: the time links of the boundary-adjacent timeslice, host layout
+// [xs][mu][3][3]; the source timeslice starts at element site0 * 12.
+__global__ void __launch_bounds__(kBlock) sf_wall_source_kernel(long per_col, long Vs, long site0, int side, int c0,
+                                                                int ncols, const double2* __restrict__ Ut,
                                                                 double2* __restrict__ out) {
   const long total = per_col * ncols;
   for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
     const long j = k / per_col, r = k - j * per_col;
-    const long site = r / 12;
-    const int comp = (int)(r - site * 12), s = comp / 3, a = comp % 3;
+    const long site = r / 12 - site0;
+    const int comp = (int)(r % 12), s = comp / 3, a = comp % 3;
     double2 v = make_double2(0.0, 0.0);
-    if (site < Vs) {  // the first interior timeslice
+    if (site >= 0 && site < Vs) {  // the source timeslice
       const int c = c0 + (int)j, sc = c / 3, ac = c % 3;
-      // (P+)[s][sc]: 1/2 on the diagonal, -1/2 between spins s and s +- 2
-      const double pp = s == sc ? 0.5 : ((s & 1) == (sc & 1) ? -0.5 : 0.0);
-      const double2 u = U0[(site * 4 + 0) * 9 + ac * 3 + a];  // (U^+)[a][ac] = conj(U[ac][a])
-      v = make_double2(pp * u.x, -pp * u.y);
+      const double off = side == 0 ? -0.5 : 0.5;
+      const double pp = s == sc ? 0.5 : ((s & 1) == (sc & 1) ? off : 0.0);
+      if (side == 0) {  // (U^+)[a][ac] = conj(U[ac][a])
+        const double2 u = Ut[(site * 4 + 0) * 9 + ac * 3 + a];
+        v = make_double2(pp * u.x, -pp * u.y);
+      } else {  // U[a][ac]
+        const double2 u = Ut[(site * 4 + 0) * 9 + a * 3 + ac];
+        v = make_double2(pp * u.x, pp * u.y);
+      }
     }
     out[k] = v;
   }
@@ -169,14 +179,16 @@ __global__ void __launch_bounds__(kBlock) sf_wall_source_kernel(long per_col, lo
 
 }  // namespace
 
-hipError_t launch_sf_wall_sources(const Geom& g, const double2* U0, int c0, int ncols, double2* out, hipStream_t st) {
-  if (ncols <= 0 || c0 < 0 || c0 + ncols > 12) return hipErrorInvalidValue;
+hipError_t launch_sf_wall_sources(const Geom& g, const double2* Ut, int side, int c0, int ncols, double2* out,
+                                  hipStream_t st) {
+  if (ncols <= 0 || c0 < 0 || c0 + ncols > 12 || (side != 0 && side != 1)) return hipErrorInvalidValue;
   const long per_col = 2L * g.Vh * 12;
   const long Vs = 2L * g.Vsh;
+  const long site0 = side == 0 ? 0 : (long)(g.T - 1) * Vs;
   const long total = per_col * ncols;
   const long blocks = std::min<long>((total + kBlock - 1) / kBlock, 8L * 1024);
-  hipLaunchKernelGGL(sf_wall_source_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, per_col, Vs, c0, ncols, U0,
-                     out);
+  hipLaunchKernelGGL(sf_wall_source_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, per_col, Vs, site0, side, c0,
+                     ncols, Ut, out);
   return hipGetLastError();
 }
 

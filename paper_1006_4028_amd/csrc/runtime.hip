@@ -663,13 +663,17 @@ int dp_set_gauge_sf(dp_ctx* c, const double* U_ext, double ct_tilde) {
   return DP_OK;
 }
 
-int dp_sf_wall_sources(dp_ctx* c, int c0, int ncols, void* eta, void* stream) {
+int dp_sf_wall_sources(dp_ctx* c, int side, int c0, int ncols, void* eta, void* stream) {
   if (!c || !eta) return fail(c, DP_ERR_INVALID_ARG, "null argument");
+  if (side != 0 && side != 1) return fail(c, DP_ERR_INVALID_ARG, "side must be 0 (x0 = 0) or 1 (x0 = T + 1)");
   if (c0 < 0 || ncols < 1 || c0 + ncols > 12) return fail(c, DP_ERR_INVALID_ARG, "need 0 <= c0 and c0 + ncols <= 12");
   if (!c->sf) return fail(c, DP_ERR_BAD_STATE, "no Schroedinger-functional links set (dp_set_gauge_sf)");
   DP_HIP(c, hipSetDevice(c->device));
   if (stream) DP_HIP(c, hipStreamSynchronize((hipStream_t)stream));
-  DP_HIP(c, launch_sf_wall_sources(c->g, c->sf_ext.as<double2>(), c0, ncols, static_cast<double2*>(eta), c->stream));
+  // the padded timeslice next to the boundary: x0 = 0 or x0 = T
+  const size_t per_t = (size_t)2 * c->g.Vsh * 4 * 9;
+  const double2* Ut = c->sf_ext.as<double2>() + (side == 0 ? 0 : per_t * c->g.T);
+  DP_HIP(c, launch_sf_wall_sources(c->g, Ut, side, c0, ncols, static_cast<double2*>(eta), c->stream));
   DP_HIP(c, hipStreamSynchronize(c->stream));
   return DP_OK;
 }
