@@ -149,22 +149,39 @@ class Server:
             self.workers[name] = FieldWorker(name, L, nslots, precision, r, max_iter, k, budget, self.mem_lock,
                                              self.mem)
 
-    def run(self, requests):
+    def run(self, requests, progress=0):
         """Submit the requests at their arrival offsets (seconds, request.t_arrival
-        relative to the start); return the requests when all are finished."""
+        relative to the start); return the requests when all are finished.
+        progress > 0 logs the submitted and finished counts to stderr every
+        `progress` submissions and whenever the finished count changes while
+        the last requests drain (checked every 10 s)."""
+        import sys
         for w in self.workers.values():
             w.start()
         t0 = time.perf_counter()
-        for req in sorted(requests, key=lambda q: q.t_arrival):
+        reqs = sorted(requests, key=lambda q: q.t_arrival)
+
+        def finished():
+            return sum(q.status not in ("", "queued", "running") for q in reqs)
+
+        for k, req in enumerate(reqs, 1):
             delay = t0 + req.t_arrival - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
             req.t_arrival = time.perf_counter()
             self.workers[req.field].q.put(req)
+            if progress and k % progress == 0:
+                print(f"  {k}/{len(reqs)} submitted, {finished()} finished", file=sys.stderr, flush=True)
         for w in self.workers.values():
             w.closing = True
+        last = -1
         for w in self.workers.values():
-            w.join()
+            while w.is_alive():
+                w.join(timeout=10.0)
+                n = finished()
+                if progress and n != last:
+                    print(f"  draining: {n}/{len(reqs)} finished", file=sys.stderr, flush=True)
+                    last = n
             if w.error:
                 raise w.error
         self.t_start, self.t_end = t0, time.perf_counter()
@@ -205,7 +222,7 @@ def summarize(server, reqs):
                 p99_ms=float(np.percentile(lat, 99) * 1e3), mean_slot_occupancy=float(np.mean(occ)) if occ else 0.0)
 
 
-def sweep(loads=(0.5, 0.8, 1.0, 1.2), requests=150, r=1e-10, seed=2024, nslots=24, out=None):
+def sweep(loads=(0.5, 0.8, 1.0, 1.2), requests=150, r=1e-10, seed=2024, nslots=24, out=None, progress=0):
     """The served-stream measurement: resident 16^3x32 and 24^3x48 fields, the
     FP64-inner capacity measured first (a saturating stream), then Poisson
     streams at the given fractions of that capacity, FP32 and FP64 inner, each
@@ -223,7 +240,7 @@ def sweep(loads=(0.5, 0.8, 1.0, 1.2), requests=150, r=1e-10, seed=2024, nslots=2
         reqs = poisson_requests(n, rate, fields, T_of, seed=seed)
         srv = Server(fields, nslots=nslots, precision=prec, r=r, max_iter=20000, k=4)
         try:
-            s = summarize(srv, srv.run(reqs))
+            s = summarize(srv, srv.run(reqs, progress=progress))
         finally:
             srv.close()
         rec = dict(precision=prec, rate_per_s=rate, r=r, **s)
@@ -252,6 +269,7 @@ if __name__ == "__main__":
     ap.add_argument("--r", type=float, default=1e-10)
     ap.add_argument("--loads", default="0.5,0.8,1.0,1.2")
     ap.add_argument("--out", default=None, help="also append the JSON records to this file")
+    ap.add_argument("--progress", type=int, default=0, help="log progress every N submitted requests")
     a = ap.parse_args()
     f = open(a.out, "a") if a.out else None
-    sweep(tuple(float(x) for x in a.loads.split(",")), a.requests, a.r, out=f)
+    sweep(tuple(float(x) for x in a.loads.split(",")), a.requests, a.r, out=f, progress=a.progress)
