@@ -168,7 +168,9 @@ int dp_sf_wall_sources(dp_ctx* ctx, int side, int c0, int ncols, void* eta_dev, 
 int dp_set_clover(dp_ctx* ctx, double csw);
 /* A caller-supplied clover field, host layout [site][12][12]; it must be
  * Hermitian and commute with gamma5 (block diagonal in the two chiralities),
- * else DP_ERR_INVALID_ARG. */
+ * else DP_ERR_INVALID_ARG (and the term is set to zero).  It replaces the
+ * whole term: with Schroedinger-functional links the boundary counterterm
+ * is the caller's to include. */
 int dp_set_clover_field(dp_ctx* ctx, const double* C);
 
 /* Paper: the quark mass M of eq. linsysunprec (the hopping parameters of
