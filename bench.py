@@ -341,6 +341,7 @@ def main():
                                     "GBps": round(V * 264 * 8 / t_ap / 1e9, 2)})
             log(f"  oracle operator on {n} threads: {1e3 * t_ap:.1f} ms")
         oracle.set_threads(nthr)
+        cpu["configs"] = oracle_config_timings(oracle, nthr)
 
     traffic = measured_traffic()
     L.close()
@@ -422,6 +423,41 @@ def sap_study():
 
 
 MALL_BYTES = 256 * 2 ** 20
+
+
+def oracle_config_timings(oracle, nthr):
+    """The oracle on the other workloads, all threads: one FP64 BiCGStab column
+    to r = 1e-11 on the free 8^3x16 and the 16^3x32 fields, and the
+    full-lattice operator (GB/s as for the main workload) on those and on
+    32^3x64 (its light-mass solve is left out: hundreds of iterations)."""
+    import numpy as np
+    import synth
+    out = []
+    for name in ("free_8c16", "su3_16c32", "su3_32c64"):
+        cfg = synth.config(name)
+        dims = cfg["dims"]
+        U = synth.free_gauge(dims) if cfg["eps"] == 0 else synth.gauge_su3(dims, cfg["eps"], cfg["seed"])
+        C = None if cfg["csw"] == 0 else oracle.clover(U, cfg["csw"])
+        M = cfg["masses"][0]
+        alpha = synth.alpha_table(cfg["profile"], dims[0], cfg["alpha0s"][-1])
+        eta = synth.point_sources_12(dims, (0, 0, 0, 0), 1)[0]
+        V = int(np.prod(dims))
+        rec = {"workload": name, "threads": nthr}
+        oracle.apply(U, C, M, eta, alpha=alpha)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            oracle.apply(U, C, M, eta, alpha=alpha)
+        t_ap = (time.perf_counter() - t0) / 3
+        rec["operator_ms"] = round(1e3 * t_ap, 2)
+        rec["operator_GBps"] = round(V * 264 * 8 / t_ap / 1e9, 2)
+        if name != "su3_32c64":
+            t0 = time.perf_counter()
+            _, info = oracle.solve(U, C, M, eta, alpha=alpha, r=1e-11)
+            rec["solve_s"] = round(time.perf_counter() - t0, 3)
+            rec["solve_iters"] = info["iters"]
+        out.append(rec)
+        log(f"  oracle {name}: {rec}")
+    return out
 
 
 def dslash_bench(args):
