@@ -570,7 +570,7 @@ __device__ __forceinline__ int slab_lo(int nch, int xcd) { return (nch * xcd) >>
 // Block j of an XCD (after the slot groups, slab kernel) is timeslice
 // j mod tlen of its range and chunk j / tlen; blocks past the range or the
 // last chunk own nothing.  The reduction partial of an item is x0 nch +
-// chunk (nparts = T nch), the same in both kernels.
+// chunk (nparts = T nch), the same in both kernels and in the slab mapping.
 struct Item {
   int chunk, x0, part;
   bool in;
@@ -623,11 +623,11 @@ __global__ void __launch_bounds__(64) hop_kernel_slab(HopArgs a, SlabMap m) {
   // shared-tile kernel (measured on MI355X: 2% on the 12-slot FP16 kernel)
   if constexpr (EPI == EPI_DIAG) x0 = a.g.T - 1 - x0;
   const int chunk = slab_lo(m.nch, xcd) + cl;
-  const bool in_slab = chunk < slab_lo(m.nch, xcd + 1);
+  if (chunk >= slab_lo(m.nch, xcd + 1)) return;  // past the slab: owns no partial
   const int sp = chunk * 64 + threadIdx.x;
-  const bool valid = in_slab && sp < a.g.Vsh;
+  const bool valid = sp < a.g.Vsh;
   const int i = valid ? x0 * a.g.Vsh + sp : 0;
-  site_work<P, EPI, RED, NS, NT, DAG>(a, grp, i, valid, (xcd * a.g.T + x0) * m.maxc + cl, 8 * a.g.T * m.maxc);
+  site_work<P, EPI, RED, NS, NT, DAG>(a, grp, i, valid, x0 * m.nch + chunk, a.g.T * m.nch);
 }
 
 // Shared-tile mapping: the slab mapping's (XCD chunk, timeslice) with every
@@ -689,27 +689,23 @@ __global__ void __launch_bounds__(shared_max_threads<P>(RED), shared_min_waves<P
   // timeslices are then still in the caches (measured on MI355X at 24^3x48
   // with 12 slots: 3% faster).  The reduction partials are indexed by x0, so
   // the sums do not depend on the order.
-  int chunk, x0, part, nparts;
-  bool in_slab;
+  int chunk, x0;
   if (m.tmap) {
     const Item it = time_item(m, g.T, xcd, j, EPI == EPI_DIAG);
     if (!it.in) return;  // the whole workgroup owns no partial (before any barrier)
     chunk = it.chunk;
     x0 = it.x0;
-    part = it.part;
-    nparts = g.T * m.nch;
-    in_slab = true;
   } else {
     const int cl = j % m.maxc;
     x0 = EPI == EPI_DIAG ? g.T - 1 - j / m.maxc : j / m.maxc;
     chunk = slab_lo(m.nch, xcd) + cl;
-    in_slab = chunk < slab_lo(m.nch, xcd + 1);
-    part = (xcd * g.T + x0) * m.maxc + cl;
-    nparts = 8 * g.T * m.maxc;
+    if (chunk >= slab_lo(m.nch, xcd + 1)) return;  // past the slab (before any barrier)
   }
+  // one reduction partial per (timeslice, chunk), whatever the mapping
+  const int part = x0 * m.nch + chunk, nparts = g.T * m.nch;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int sp = chunk * 64 + lane;
-  const bool valid = in_slab && sp < g.Vsh;
+  const bool valid = sp < g.Vsh;
   const int i = valid ? x0 * g.Vsh + sp : 0;
   // fill: tasks 0..7 are the link directions (2 mu forward, 2 mu + 1 backward),
   // task 8 the clover blocks (even-site epilogue) or the A^-1 blocks all
@@ -799,13 +795,18 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
     // tuning knob: DP_HOP_ORDER in {0, 1, 2} (block order within an XCD)
     static const int order = std::min(2, std::max(0, env_knob("DP_HOP_ORDER", 0)));
     m.order = order;
-    // tuning knob: DP_HOP_TMAP = 1 gives each XCD a range of timeslices
-    // instead of a spatial slab (time_item)
-    static const int tmap = env_knob("DP_HOP_TMAP", 0) == 1 ? 1 : 0;
+    // XCD mapping: spatial slabs (tmap 0) or timeslice ranges (tmap 1,
+    // time_item), chosen per launch; both give one reduction partial per
+    // (timeslice, chunk), so the results are bitwise the same either way.
+    // Measured on MI355X at 24^3x48: timeslice ranges 2-5% faster for one
+    // slot and for 12 FP16 slots, slabs 6% faster for 12 FP32 slots.
+    // Tuning knob: DP_HOP_TMAP = 0 / 1 forces one of them.
+    static const int tmap_knob = env_knob("DP_HOP_TMAP", -1);
+    const int tmap = tmap_knob == 0 || tmap_knob == 1 ? tmap_knob : (a.nslots == 1 || P == F16 ? 1 : 0);
     m.tmap = tmap;
     m.tlen = (a.g.T + 7) / 8;
-    nparts = tmap ? a.g.T * m.nch : 8 * a.g.T * m.maxc;
-    const int nblocks = tmap ? 8 * m.tlen * m.nch : nparts;  // blocks per slot group
+    nparts = a.g.T * m.nch;
+    const int nblocks = tmap ? 8 * m.tlen * m.nch : 8 * a.g.T * m.maxc;  // blocks per slot group
     const dim3 grid(nblocks * ngroups);
     // tuning knob: DP_HOP_LDS = bytes of (unused) LDS per block, which caps the
     // blocks resident per CU (160 KB of LDS per CU) and so the sweep front
