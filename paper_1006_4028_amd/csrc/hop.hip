@@ -798,11 +798,14 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
     // XCD mapping: spatial slabs (tmap 0) or timeslice ranges (tmap 1,
     // time_item), chosen per launch; both give one reduction partial per
     // (timeslice, chunk), so the results are bitwise the same either way.
-    // Measured on MI355X at 24^3x48: timeslice ranges 2-5% faster for one
-    // slot and for 12 FP16 slots, slabs 6% faster for 12 FP32 slots.
-    // Tuning knob: DP_HOP_TMAP = 0 / 1 forces one of them.
+    // Measured on MI355X: timeslice ranges 2-6% faster for one FP32 or FP16
+    // slot and for 12 FP16 slots at 24^3x48 and 32^3x64, slabs 6% faster for
+    // 12 FP32 slots; FP64 keeps the slabs (one slot: 2% faster on timeslice
+    // ranges at 24^3x48, 4-10% slower at 32^3x64).  Tuning knob:
+    // DP_HOP_TMAP = 0 / 1 forces one of them.
     static const int tmap_knob = env_knob("DP_HOP_TMAP", -1);
-    const int tmap = tmap_knob == 0 || tmap_knob == 1 ? tmap_knob : (a.nslots == 1 || P == F16 ? 1 : 0);
+    const int tmap = tmap_knob == 0 || tmap_knob == 1 ? tmap_knob
+                                                      : (P != F64 && (a.nslots == 1 || P == F16) ? 1 : 0);
     m.tmap = tmap;
     m.tlen = (a.g.T + 7) / 8;
     nparts = a.g.T * m.nch;
