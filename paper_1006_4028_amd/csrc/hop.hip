@@ -817,16 +817,15 @@ hipError_t launch_ns(const HopArgs& a, int ntiles, hipStream_t st, int* nparts_o
     // Two or more slots in FP32 or FP16: the shared-tile kernel, one slot per
     // wave (measured on MI355X at 24^3x48 with 12 slots: FP32 16% faster
     // than the slab kernel with two slots per thread, FP16 12% faster on the
-    // even sites).  Not for the FP16 kernels with the four-term reduction or
-    // the reconstruction epilogue: at the shared-tile kernel's two waves per
-    // SIMD they spill.  One slot: the slab kernel (a one-wave shared-tile
+    // even sites).  Not for the FP16 reconstruction epilogue: at the
+    // shared-tile kernel's two waves per SIMD it spills.  One slot: the slab kernel (a one-wave shared-tile
     // workgroup holds as much LDS as a full one, and the CUs would run one
     // wave each).  The library is built with contraction limited to single
     // expressions, so both kernels round alike and a slot's results are
     // bitwise the same alone and in any batch.  Tuning knob: DP_HOP_SHARED
     // = 0 keeps one workgroup per slot group.
     static const bool shared = env_knob("DP_HOP_SHARED", 1) == 1;
-    constexpr bool shared_ok = P == F32 || (P == F16 && RED != RED_TS4 && EPI != EPI_INV_SUB);
+    constexpr bool shared_ok = P == F32 || (P == F16 && EPI != EPI_INV_SUB);
     if constexpr (shared_ok) {
       if (shared && nt && !forced && a.nslots >= 2) {
         m.ngroups = a.nslots;
