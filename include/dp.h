@@ -263,6 +263,21 @@ typedef struct {
 /* One right-hand side (host layout); S and cpp (T doubles) nullable. */
 int dp_solve_sap(dp_ctx* ctx, const double* eta, const dp_sap_params* p, double* S, double* cpp, dp_info* info);
 
+/* Paper: the Schwarz preconditioner of the solver of Table 1 (the procedure
+ * it cites), on the preconditioned operator D' of eqs. redefa, betaa.
+ * One application psi = M r of the SAP preconditioner that dp_solve_sap uses
+ * inside GCR: psi = 0, then ncy cycles over the two block colours, each
+ * forming the block residual r - D' psi on the blocks of the colour and
+ * running nmr minimal-residual steps of the Dirichlet block operator on it
+ * (block sums in FP64).  r and psi: host layout, V x 12 complex doubles,
+ * already in the preconditioned variables (no beta is applied).  Uses
+ * p->block, ncy, nmr and precision (validated as for dp_solve_sap); r, nkv
+ * and max_iter are ignored.  With FP32 block solves on blocks of at most
+ * 256 sites one kernel runs each colour pass (block solves in registers and
+ * LDS); larger blocks and FP64 launch the operator per minimal-residual
+ * step.  Returns DP_ERR_INVALID_ARG / DP_ERR_BAD_STATE as dp_solve_sap. */
+int dp_sap_precondition(dp_ctx* ctx, const double* r, const dp_sap_params* p, double* psi);
+
 /* Instrumentation (no passage of the paper: it reports no timings).
  * Per-kernel timing of the library's own launches.  dp_set_timing(ctx, 1)
  * clears the statistics and brackets every later kernel launch of the ctx

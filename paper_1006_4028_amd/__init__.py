@@ -269,6 +269,17 @@ class Lattice:
         self._check(rc, allow=(L.DP_ERR_NOT_CONVERGED,) if allow_unconverged else ())
         return S, cpp, self._infos([info])[0]
 
+    def sap_precondition(self, r, block, ncy=5, nmr=4, precision="f32"):
+        """One application psi = M r of the SAP preconditioner (host layout,
+        preconditioned variables)."""
+        r = _c128(r)
+        assert r.size == self.V * 12
+        psi = np.zeros_like(r)
+        p = L.dp_sap_params(1.0, (ctypes.c_int * 4)(*[int(b) for b in block]), int(ncy), int(nmr), 1,
+                            L.DP_PREC[precision], 1)
+        self._check(self._L.dp_sap_precondition(self._h, _ptr(r), ctypes.byref(p), _ptr(psi)))
+        return psi
+
     def solve_dev(self, eta_t, S_t=None, r=1e-11, solver="bicgstab", precision="f64", max_iter=10000, delta=0.0,
                   x0_src=0, ncols_group=0, allow_unconverged=False, allow=()):
         """Device variant: eta_t (and S_t) are torch CUDA tensors in host layout."""

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <complex>
 #include <vector>
 
@@ -224,6 +225,438 @@ __global__ void __launch_bounds__(kBlock) vec_dot_kernel(Geom g, SpinorRef x, Sp
   }
 }
 
+// ------------------------------------------------------- fused block solves
+//
+// For blocks of at most kSapThreads sites the whole pass over one colour (the
+// block residual, then nmr minimal-residual steps) runs as one kernel: a
+// workgroup per block and a thread per site.  Each thread keeps its site's
+// four forward links and clover blocks in registers for the pass; the block
+// residual rho lives in LDS.  Of the hops inside a block, the forward one at x
+// reads rho(x + mu) from LDS and multiplies by the thread's own link; the
+// backward one at x needs U_mu(x - mu)^+ applied to rho(x - mu), which the
+// thread of x - mu forms with its own link and leaves in LDS for x.  Hops that
+// leave the block drop (Dirichlet block boundaries).
+//
+// The fields of the pass are stored block by block ("block layout"): the
+// blocks of colour 0 in the order of their index k, then those of colour 1;
+// each block as component arrays over its sites s = ((l0 b1 + l1) b2 + l2) b3
+// + l3 (l = coordinates within the block), so that the lanes of a wave, one
+// site each, read consecutive addresses.  Spinors: float4 [6][vol] per block
+// (components 2q, 2q + 1); links: float2 [4][9][vol]; clover: float4 [18][vol]
+// (the packed blocks of the parity fields).
+
+constexpr int kSapThreads = 256;
+
+struct BLoc {
+  int blk, s;
+};
+
+// block-layout position of site x
+__device__ __forceinline__ BLoc bl_locate(const Blocking& b, int x0, int x1, int x2, int x3) {
+  const int c0 = x0 / b.bs[0], c1 = x1 / b.bs[1], c2 = x2 / b.bs[2], c3 = x3 / b.bs[3];
+  const int colour = (c0 + c1 + c2 + c3) & 1;
+  const int k = ((c0 * b.nb[1] + c1) * b.nb[2] + c2) * (b.nb[3] / 2) + c3 / 2;
+  const int s = (((x0 - c0 * b.bs[0]) * b.bs[1] + (x1 - c1 * b.bs[1])) * b.bs[2] + (x2 - c2 * b.bs[2])) * b.bs[3] +
+                (x3 - c3 * b.bs[3]);
+  return {colour * b.nhalf + k, s};
+}
+
+// FP32 links and clover of both parities -> block layout
+__global__ void __launch_bounds__(kBlock) sap_gather_kernel(Geom g, Blocking b, const float2* __restrict__ U0,
+                                                            const float2* __restrict__ U1,
+                                                            const float4* __restrict__ C0,
+                                                            const float4* __restrict__ C1, float2* __restrict__ ubl,
+                                                            float4* __restrict__ cbl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (i >= g.Vh) return;
+  int x0, x1, x2, x3;
+  eo_coords(g, p, i, x0, x1, x2, x3);
+  const BLoc q = bl_locate(b, x0, x1, x2, x3);
+  const float2* U = p ? U1 : U0;
+  const float4* C = p ? C1 : C0;
+  for (int k = 0; k < 36; ++k) ubl[((long)q.blk * 36 + k) * b.vol + q.s] = U[(long)k * g.Vp + i];
+  for (int k = 0; k < 18; ++k) cbl[((long)q.blk * 18 + k) * b.vol + q.s] = C[(long)k * g.Vp + i];
+}
+
+// FP64 parity fields -> FP32 block layout
+__global__ void __launch_bounds__(kBlock) sap_to_block_kernel(Geom g, Blocking b, SpinorRef x,
+                                                              float4* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (i >= g.Vh) return;
+  int x0, x1, x2, x3;
+  eo_coords(g, p, i, x0, x1, x2, x3);
+  const BLoc q = bl_locate(b, x0, x1, x2, x3);
+  cx<double> v[12];
+  SpinorIO<F64>::load(x, p, i, g.Vp, v);
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    out[((long)q.blk * 6 + k) * b.vol + q.s] =
+        make_float4((float)v[2 * k].x, (float)v[2 * k].y, (float)v[2 * k + 1].x, (float)v[2 * k + 1].y);
+}
+
+// FP32 block layout -> FP64 parity fields
+__global__ void __launch_bounds__(kBlock) sap_from_block_kernel(Geom g, Blocking b, const float4* __restrict__ in,
+                                                                SpinorRef y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (i >= g.Vh) return;
+  int x0, x1, x2, x3;
+  eo_coords(g, p, i, x0, x1, x2, x3);
+  const BLoc q = bl_locate(b, x0, x1, x2, x3);
+  cx<double> v[12];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const float4 f = in[((long)q.blk * 6 + k) * b.vol + q.s];
+    v[2 * k] = cx<double>{f.x, f.y};
+    v[2 * k + 1] = cx<double>{f.z, f.w};
+  }
+  SpinorIO<F64>::store(y, p, i, g.Vp, v);
+}
+
+// Spin projection in the chiral basis (psi = (u0, u1, l0, l1) in spin, as in
+// the hop kernels): (1 - sg gamma_mu) psi is determined by its upper half h;
+// the lower half is a fixed spin rotation of h.
+template <int MU, int SG>
+__device__ __forceinline__ void bl_proj(const cx<float> (&v)[12], cx<float> (&h)[6]) {
+  constexpr float sg = (float)SG;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const cx<float> u0 = v[a], u1 = v[3 + a], l0 = v[6 + a], l1 = v[9 + a];
+    if constexpr (MU == 0) {
+      h[a] = u0 + sg * l0;
+      h[3 + a] = u1 + sg * l1;
+    } else if constexpr (MU == 1) {
+      h[a] = u0 + sg * ti(l1);
+      h[3 + a] = u1 + sg * ti(l0);
+    } else if constexpr (MU == 2) {
+      h[a] = u0 + sg * l1;
+      h[3 + a] = u1 - sg * l0;
+    } else {
+      h[a] = u0 + sg * ti(l0);
+      h[3 + a] = u1 - sg * ti(l1);
+    }
+  }
+}
+
+// acc += c * (the full spinor whose upper half is w, of projector (1 - sg gamma_mu))
+template <int MU, int SG>
+__device__ __forceinline__ void bl_recon(cx<float> (&acc)[12], const cx<float> (&w)[6], float c) {
+  constexpr float sg = (float)SG;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const cx<float> w0 = c * w[a], w1 = c * w[3 + a];
+    acc[a] = acc[a] + w0;
+    acc[3 + a] = acc[3 + a] + w1;
+    if constexpr (MU == 0) {
+      acc[6 + a] = acc[6 + a] + sg * w0;
+      acc[9 + a] = acc[9 + a] + sg * w1;
+    } else if constexpr (MU == 1) {
+      acc[6 + a] = acc[6 + a] - sg * ti(w1);
+      acc[9 + a] = acc[9 + a] - sg * ti(w0);
+    } else if constexpr (MU == 2) {
+      acc[6 + a] = acc[6 + a] - sg * w1;
+      acc[9 + a] = acc[9 + a] + sg * w0;
+    } else {
+      acc[6 + a] = acc[6 + a] - sg * ti(w0);
+      acc[9 + a] = acc[9 + a] + sg * ti(w1);
+    }
+  }
+}
+
+// o = U h (DAG: U^+ h) on both spin components of a half spinor
+template <bool DAG>
+__device__ __forceinline__ void bl_link(const cx<float> (&u)[9], const cx<float> (&h)[6], cx<float> (&o)[6]) {
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<float> t;
+      if constexpr (DAG) {
+        t = cjmul(u[a], h[3 * sp]);
+        cjfma(t, u[3 + a], h[3 * sp + 1]);
+        cjfma(t, u[6 + a], h[3 * sp + 2]);
+      } else {
+        t = cmul(u[3 * a], h[3 * sp]);
+        cfma(t, u[3 * a + 1], h[3 * sp + 1]);
+        cfma(t, u[3 * a + 2], h[3 * sp + 2]);
+      }
+      o[3 * sp + a] = t;
+    }
+}
+
+__device__ __forceinline__ void bl_load_spinor(const float4* f, long base, int vol, int s, cx<float> (&v)[12]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const float4 q = f[(base + k) * vol + s];
+    v[2 * k] = cx<float>{q.x, q.y};
+    v[2 * k + 1] = cx<float>{q.z, q.w};
+  }
+}
+
+struct SapPass {
+  Geom g;
+  Blocking b;
+  int colour;
+  int nmr;
+  int own_zero;  // psi of the pass's blocks is still zero (not read)
+  const float4* r;
+  float4* psi;
+  const float2* U;
+  const float4* C;
+  const double* rt;      // time hop ratios [4][T] (fwd, bwd, ...; boundary sign folded in)
+  const double* sratio;  // spatial hop ratios of the light-quark factorisation, or null
+  float m4;              // 4 + M
+};
+
+// One pass of the Schwarz procedure over the blocks of one colour:
+// rho = r - D' psi on the block (NB_ZERO: psi = 0 everywhere, rho = r), nmr
+// minimal-residual steps with the Dirichlet block operator, psi += the
+// accumulated correction.  Block sums in FP64, reduced in a fixed order.
+template <bool NB_ZERO>
+__global__ void __launch_bounds__(kSapThreads) sap_block_kernel(SapPass a) {
+  __shared__ float rho_l[24 * kSapThreads];
+  __shared__ float hb[4 * 12 * kSapThreads];  // backward hops handed to x + mu
+  __shared__ double red[3][kSapThreads / 64];
+  __shared__ double wsh[2];
+  const Geom& g = a.g;
+  const Blocking& b = a.b;
+  const int s = threadIdx.x;
+  const bool valid = s < b.vol;
+  // the blockIdx.x-th block of the colour
+  int k = blockIdx.x;
+  const int h3 = b.nb[3] / 2;
+  int c3 = k % h3;
+  k /= h3;
+  const int c2 = k % b.nb[2];
+  k /= b.nb[2];
+  const int c1 = k % b.nb[1];
+  const int c0 = k / b.nb[1];
+  c3 = 2 * c3 + ((a.colour + c0 + c1 + c2) & 1);
+  const int blk = a.colour * b.nhalf + blockIdx.x;
+  const int st[4] = {b.bs[1] * b.bs[2] * b.bs[3], b.bs[2] * b.bs[3], b.bs[3], 1};
+  int l[4];
+  {
+    int t = valid ? s : 0;
+    l[3] = t % b.bs[3];
+    t /= b.bs[3];
+    l[2] = t % b.bs[2];
+    t /= b.bs[2];
+    l[1] = t % b.bs[1];
+    l[0] = t / b.bs[1];
+  }
+  const int x[4] = {c0 * b.bs[0] + l[0], c1 * b.bs[1] + l[1], c2 * b.bs[2] + l[2], c3 * b.bs[3] + l[3]};
+  const int Ls[4] = {g.T, g.L1, g.L2, g.L3};
+  // hop coefficients: time ratios, spatial ratios (or 1)
+  float cf[4], cb[4];
+  cf[0] = (float)a.rt[x[0]];
+  cb[0] = (float)a.rt[g.T + x[0]];
+  {
+    int off = 0;
+#pragma unroll
+    for (int mu = 1; mu < 4; ++mu) {
+      cf[mu] = a.sratio ? (float)a.sratio[off + x[mu]] : 1.f;
+      cb[mu] = a.sratio ? (float)a.sratio[off + Ls[mu] + x[mu]] : 1.f;
+      off += 4 * Ls[mu];
+    }
+  }
+  // the site's forward links and clover blocks, kept for the pass
+  cx<float> U[4][9];
+  HermBlock<float> B[2];
+  {
+    const long ub = (long)blk * 36;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const float2 v = a.U[(ub + mu * 9 + q) * b.vol + s * valid];
+        U[mu][q] = cx<float>{v.x, v.y};
+      }
+    float raw[72];
+#pragma unroll
+    for (int q = 0; q < 18; ++q) {
+      const float4 v = a.C[((long)blk * 18 + q) * b.vol + s * valid];
+      raw[4 * q] = v.x;
+      raw[4 * q + 1] = v.y;
+      raw[4 * q + 2] = v.z;
+      raw[4 * q + 3] = v.w;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) B[h].d[q] = raw[36 * h + q];
+#pragma unroll
+      for (int q = 0; q < 15; ++q) B[h].o[q] = cx<float>{raw[36 * h + 6 + 2 * q], raw[36 * h + 7 + 2 * q]};
+    }
+  }
+  // block residual
+  if (valid) {
+    cx<float> rv[12];
+    bl_load_spinor(a.r, (long)blk * 6, b.vol, s, rv);
+    if constexpr (!NB_ZERO) {
+      cx<float> acc[12], out[12], v[12], h[6], w[6];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        acc[c] = cx<float>{0.f, 0.f};
+        out[c] = cx<float>{0.f, 0.f};
+      }
+      if (!a.own_zero) {
+        bl_load_spinor(a.psi, (long)blk * 6, b.vol, s, v);
+        herm_apply(B[0], a.m4, &v[0], &out[0]);
+        herm_apply(B[1], a.m4, &v[6], &out[6]);
+      }
+      // the eight neighbours, inside or outside the block
+#define DP_SAP_RES_DIR(MU)                                                                         \
+  {                                                                                                \
+    int y[4] = {x[0], x[1], x[2], x[3]};                                                           \
+    y[MU] = x[MU] + 1 == Ls[MU] ? 0 : x[MU] + 1;                                                   \
+    BLoc q = bl_locate(b, y[0], y[1], y[2], y[3]);                                                 \
+    if (!(a.own_zero && q.blk == blk)) {                                                           \
+      bl_load_spinor(a.psi, (long)q.blk * 6, b.vol, q.s, v);                                       \
+      bl_proj<MU, 1>(v, h);                                                                        \
+      bl_link<false>(U[MU], h, w);                                                                 \
+      bl_recon<MU, 1>(acc, w, cf[MU]);                                                             \
+    }                                                                                              \
+    y[MU] = x[MU] == 0 ? Ls[MU] - 1 : x[MU] - 1;                                                   \
+    q = bl_locate(b, y[0], y[1], y[2], y[3]);                                                      \
+    if (!(a.own_zero && q.blk == blk)) {                                                           \
+      cx<float> ub[9];                                                                             \
+      for (int e = 0; e < 9; ++e) {                                                                \
+        const float2 t = a.U[((long)q.blk * 36 + MU * 9 + e) * b.vol + q.s];                       \
+        ub[e] = cx<float>{t.x, t.y};                                                               \
+      }                                                                                            \
+      bl_load_spinor(a.psi, (long)q.blk * 6, b.vol, q.s, v);                                       \
+      bl_proj<MU, -1>(v, h);                                                                       \
+      bl_link<true>(ub, h, w);                                                                     \
+      bl_recon<MU, -1>(acc, w, cb[MU]);                                                            \
+    }                                                                                              \
+  }
+      DP_SAP_RES_DIR(0)
+      DP_SAP_RES_DIR(1)
+      DP_SAP_RES_DIR(2)
+      DP_SAP_RES_DIR(3)
+#undef DP_SAP_RES_DIR
+#pragma unroll
+      for (int c = 0; c < 12; ++c) rv[c] = rv[c] - (out[c] + (-0.5f) * acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      rho_l[(2 * c) * kSapThreads + s] = rv[c].x;
+      rho_l[(2 * c + 1) * kSapThreads + s] = rv[c].y;
+    }
+  }
+  cx<float> dpsi[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) dpsi[c] = cx<float>{0.f, 0.f};
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int it = 0; it < a.nmr; ++it) {
+    __syncthreads();  // rho complete
+    cx<float> rv[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rv[c] = cx<float>{rho_l[(2 * c) * kSapThreads + s], rho_l[(2 * c + 1) * kSapThreads + s]};
+    // hand the backward hops to the sites x + mu of the block
+    if (valid) {
+      cx<float> h[6], w[6];
+#define DP_SAP_PUSH(MU)                                                       \
+  if (l[MU] + 1 < b.bs[MU]) {                                                 \
+    bl_proj<MU, -1>(rv, h);                                                   \
+    bl_link<true>(U[MU], h, w);                                               \
+    for (int e = 0; e < 6; ++e) {                                             \
+      hb[((MU * 12) + 2 * e) * kSapThreads + s + st[MU]] = w[e].x;            \
+      hb[((MU * 12) + 2 * e + 1) * kSapThreads + s + st[MU]] = w[e].y;        \
+    }                                                                         \
+  }
+      DP_SAP_PUSH(0)
+      DP_SAP_PUSH(1)
+      DP_SAP_PUSH(2)
+      DP_SAP_PUSH(3)
+#undef DP_SAP_PUSH
+    }
+    __syncthreads();
+    // av = D'_B rho at x
+    cx<float> av[12];
+    double nr = 0.0, ni = 0.0, dn = 0.0;
+    if (valid) {
+      cx<float> acc[12], v[12], h[6], w[6];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[c] = cx<float>{0.f, 0.f};
+#define DP_SAP_PULL(MU)                                                                                      \
+  if (l[MU] + 1 < b.bs[MU]) {                                                                                \
+    const int n = s + st[MU];                                                                                \
+    for (int c = 0; c < 12; ++c) v[c] = cx<float>{rho_l[(2 * c) * kSapThreads + n], rho_l[(2 * c + 1) * kSapThreads + n]}; \
+    bl_proj<MU, 1>(v, h);                                                                                    \
+    bl_link<false>(U[MU], h, w);                                                                             \
+    bl_recon<MU, 1>(acc, w, cf[MU]);                                                                         \
+  }                                                                                                          \
+  if (l[MU] > 0) {                                                                                           \
+    for (int e = 0; e < 6; ++e)                                                                              \
+      w[e] = cx<float>{hb[((MU * 12) + 2 * e) * kSapThreads + s], hb[((MU * 12) + 2 * e + 1) * kSapThreads + s]}; \
+    bl_recon<MU, -1>(acc, w, cb[MU]);                                                                        \
+  }
+      DP_SAP_PULL(0)
+      DP_SAP_PULL(1)
+      DP_SAP_PULL(2)
+      DP_SAP_PULL(3)
+#undef DP_SAP_PULL
+      herm_apply(B[0], a.m4, &rv[0], &av[0]);
+      herm_apply(B[1], a.m4, &rv[6], &av[6]);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        av[c] = av[c] + (-0.5f) * acc[c];
+        nr += (double)av[c].x * (double)rv[c].x + (double)av[c].y * (double)rv[c].y;
+        ni += (double)av[c].x * (double)rv[c].y - (double)av[c].y * (double)rv[c].x;
+        dn += (double)av[c].x * (double)av[c].x + (double)av[c].y * (double)av[c].y;
+      }
+    }
+    // w = <a, rho>_B / |a|^2_B
+    nr = wave_sum(nr);
+    ni = wave_sum(ni);
+    dn = wave_sum(dn);
+    if (lane == 0) {
+      red[0][wv] = nr;
+      red[1][wv] = ni;
+      red[2][wv] = dn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sr = 0.0, si = 0.0, sd = 0.0;
+      for (int q = 0; q < kSapThreads / 64; ++q) {
+        sr += red[0][q];
+        si += red[1][q];
+        sd += red[2][q];
+      }
+      wsh[0] = sd > 0.0 ? sr / sd : 0.0;
+      wsh[1] = sd > 0.0 ? si / sd : 0.0;
+    }
+    __syncthreads();
+    if (valid) {
+      const cx<float> w{(float)wsh[0], (float)wsh[1]};
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        dpsi[c] = dpsi[c] + cmul(w, rv[c]);
+        rv[c] = rv[c] - cmul(w, av[c]);
+        rho_l[(2 * c) * kSapThreads + s] = rv[c].x;
+        rho_l[(2 * c + 1) * kSapThreads + s] = rv[c].y;
+      }
+    }
+  }
+  if (valid) {
+    cx<float> v[12];
+    if (a.own_zero) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) v[c] = dpsi[c];
+    } else {
+      bl_load_spinor(a.psi, (long)blk * 6, b.vol, s, v);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) v[c] = v[c] + dpsi[c];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      a.psi[((long)blk * 6 + q) * b.vol + s] = make_float4(v[2 * q].x, v[2 * q].y, v[2 * q + 1].x, v[2 * q + 1].y);
+  }
+}
+
 constexpr int kDotBlocks = 1024;
 
 }  // namespace
@@ -238,6 +671,9 @@ struct SapState {
   std::vector<Field> z, w;  // FP64, nkv each
   Field q_r, q_psi, q_rho, q_a;  // block-solve precision
   DevBuf ratio, m4, partials, alpha, cpp;
+  // fused block solves: links, clover, r and psi in block layout (FP32)
+  bool fused = false;
+  DevBuf ubl, cbl, rbl, pbl;
   std::vector<double> h_part;
 };
 
@@ -359,9 +795,65 @@ int sap_apply(dp_ctx* c, SapState& s, const Blocking& b, int ncy, int nmr) {
   return DP_OK;
 }
 
+// The fused block solves take FP32 block solves on blocks of at most
+// kSapThreads sites (DP_SAP_FUSED=0 keeps the launch-per-step path).
+bool sap_fused_enabled(int prec, const Blocking& b) {
+  if (prec != F32 || b.vol > kSapThreads) return false;
+  const char* e = std::getenv("DP_SAP_FUSED");
+  return !(e && e[0] == '0');
+}
+
+// block-layout buffers and the links and clover gathered into them
+int sap_fused_setup(dp_ctx* c, SapState& s, const Blocking& b) {
+  const long V = 2L * c->g.Vh;
+  DP_HIP(c, s.ubl.reserve(sizeof(float2) * 36 * V));
+  DP_HIP(c, s.cbl.reserve(sizeof(float4) * 18 * V));
+  DP_HIP(c, s.rbl.reserve(sizeof(float4) * 6 * V));
+  DP_HIP(c, s.pbl.reserve(sizeof(float4) * 6 * V));
+  hipLaunchKernelGGL(sap_gather_kernel, site_grid(c->g), dim3(kBlock), 0, c->stream, c->g, b,
+                     c->U[F32][0].as<float2>(), c->U[F32][1].as<float2>(), c->C32[0].as<float4>(),
+                     c->C32[1].as<float4>(), s.ubl.as<float2>(), s.cbl.as<float4>());
+  DP_HIP(c, hipGetLastError());
+  return DP_OK;
+}
+
+// psi = M r with one kernel per colour pass (r, psi in s.rbl, s.pbl)
+int sap_apply_fused(dp_ctx* c, SapState& s, const Blocking& b, int ncy, int nmr) {
+  SapPass a;
+  a.g = c->g;
+  a.b = b;
+  a.nmr = nmr;
+  a.r = s.rbl.as<float4>();
+  a.psi = s.pbl.as<float4>();
+  a.U = s.ubl.as<float2>();
+  a.C = s.cbl.as<float4>();
+  a.rt = s.ratio.as<double>();
+  a.sratio = space_hop_ratios(c);
+  a.m4 = (float)(4.0 + c->M);
+  for (int cy = 0; cy < ncy; ++cy)
+    for (int colour = 0; colour < 2; ++colour) {
+      a.colour = colour;
+      a.own_zero = cy == 0;
+      if (cy == 0 && colour == 0)
+        hipLaunchKernelGGL(sap_block_kernel<true>, dim3(b.nhalf), dim3(kSapThreads), 0, c->stream, a);
+      else
+        hipLaunchKernelGGL(sap_block_kernel<false>, dim3(b.nhalf), dim3(kSapThreads), 0, c->stream, a);
+      DP_HIP(c, hipGetLastError());
+    }
+  return DP_OK;
+}
+
 // z = M r (r, z FP64)
 int precondition(dp_ctx* c, SapState& s, const Blocking& b, int ncy, int nmr, const Field& r, const Field& z) {
-  if (s.prec == F64) {
+  if (s.fused) {
+    hipLaunchKernelGGL(sap_to_block_kernel, site_grid(c->g), dim3(kBlock), 0, c->stream, c->g, b, r.ref(),
+                       s.rbl.as<float4>());
+    DP_HIP(c, hipGetLastError());
+    DP_TRY(sap_apply_fused(c, s, b, ncy, nmr));
+    hipLaunchKernelGGL(sap_from_block_kernel, site_grid(c->g), dim3(kBlock), 0, c->stream, c->g, b,
+                       s.pbl.as<float4>(), z.ref());
+    DP_HIP(c, hipGetLastError());
+  } else if (s.prec == F64) {
     DP_TRY((convert<F64, F64>(c, r, s.q_r)));
     DP_TRY(sap_apply<F64>(c, s, b, ncy, nmr));
     DP_TRY((convert<F64, F64>(c, s.q_psi, z)));
@@ -379,11 +871,15 @@ void sap_free(SapState* s) { delete s; }
 
 }  // namespace dp
 
-extern "C" int dp_solve_sap(dp_ctx* c, const double* eta, const dp_sap_params* p, double* S, double* cpp,
-                            dp_info* info) {
-  if (!c || !eta || !p) return DP_ERR_INVALID_ARG;
+namespace dp {
+namespace {
+
+// Shared set-up of dp_solve_sap and dp_sap_precondition: the blocking, the
+// work space, the tables of the one right-hand side (time ratios, 4 + M,
+// alpha) and, for fused block solves, the block-layout links and clover.
+int sap_prepare(dp_ctx* c, const dp_sap_params* p, int nkv, Blocking* bo) {
   const Geom& g = c->g;
-  Blocking b;
+  Blocking& b = *bo;
   b.vol = 1;
   int nblocks = 1;
   for (int mu = 0; mu < 4; ++mu) {
@@ -396,9 +892,7 @@ extern "C" int dp_solve_sap(dp_ctx* c, const double* eta, const dp_sap_params* p
     nblocks *= b.nb[mu];
   }
   b.nhalf = nblocks / 2;
-  if (!(p->r > 0) || !std::isfinite(p->r) || p->ncy < 1 || p->nmr < 1 || p->nkv < 1 || p->nkv > 64 ||
-      p->max_iter < 1)
-    return fail(c, DP_ERR_INVALID_ARG, "bad residue, ncy, nmr, nkv (1..64) or max_iter");
+  if (p->ncy < 1 || p->nmr < 1) return fail(c, DP_ERR_INVALID_ARG, "bad ncy or nmr");
   if (p->precision != DP_PREC_F64 && p->precision != DP_PREC_F32)
     return fail(c, DP_ERR_INVALID_ARG, "the block solves run in FP64 or FP32");
   DP_HIP(c, hipSetDevice(c->device));
@@ -408,17 +902,51 @@ extern "C" int dp_solve_sap(dp_ctx* c, const double* eta, const dp_sap_params* p
     if (!c->sap) return fail(c, DP_ERR_OOM, "host allocation failed");
   }
   SapState& s = *c->sap;
-  DP_TRY(sap_alloc(c, s, p->nkv, p->precision));
+  DP_TRY(sap_alloc(c, s, nkv, p->precision));
+  std::vector<double> rt(4 * g.T);
+  ratio_tables(g.T, c->bc_t, c->alpha.data(), rt.data());
+  DP_TRY(h2d(c, s.ratio.p, rt.data(), sizeof(double) * 4 * g.T));
+  const double m4 = 4.0 + c->M;
+  DP_TRY(h2d(c, s.m4.p, &m4, sizeof(double)));
+  DP_TRY(h2d(c, s.alpha.p, c->alpha.data(), sizeof(double) * g.T));
+  s.fused = sap_fused_enabled(p->precision, b);
+  if (s.fused) DP_TRY(sap_fused_setup(c, s, b));
+  return DP_OK;
+}
+
+}  // namespace
+}  // namespace dp
+
+extern "C" int dp_sap_precondition(dp_ctx* c, const double* r, const dp_sap_params* p, double* psi) {
+  if (!c || !r || !p || !psi) return DP_ERR_INVALID_ARG;
+  const Geom& g = c->g;
+  Blocking b;
+  DP_TRY(sap_prepare(c, p, 1, &b));
+  SapState& s = *c->sap;
+  const size_t bytes = (size_t)2 * g.Vh * 12 * sizeof(double2);
+  DP_HIP(c, c->scratch_aos.reserve(bytes));
+  DP_HIP(c, hipMemcpyAsync(c->scratch_aos.p, r, bytes, hipMemcpyHostToDevice, c->stream));
+  for (int par = 0; par < 2; ++par)
+    DP_HIP(c, launch_spinor_import(g, c->scratch_aos.as<double2>(), 1, 0, par, s.r.ref(par), nullptr, nullptr,
+                                   c->stream));
+  DP_TRY(precondition(c, s, b, p->ncy, p->nmr, s.r, s.z[0]));
+  DP_HIP(c, launch_spinor_export(g, s.z[0].ref(0), s.z[0].ref(1), 1, nullptr, nullptr, c->scratch_aos.as<double2>(),
+                                 0, c->stream));
+  DP_HIP(c, hipMemcpyAsync(psi, c->scratch_aos.p, bytes, hipMemcpyDeviceToHost, c->stream));
+  DP_HIP(c, hipStreamSynchronize(c->stream));
+  return DP_OK;
+}
+
+extern "C" int dp_solve_sap(dp_ctx* c, const double* eta, const dp_sap_params* p, double* S, double* cpp,
+                            dp_info* info) {
+  if (!c || !eta || !p) return DP_ERR_INVALID_ARG;
+  const Geom& g = c->g;
+  if (!(p->r > 0) || !std::isfinite(p->r) || p->nkv < 1 || p->nkv > 64 || p->max_iter < 1)
+    return fail(c, DP_ERR_INVALID_ARG, "bad residue, ncy, nmr, nkv (1..64) or max_iter");
+  Blocking b;
+  DP_TRY(sap_prepare(c, p, p->nkv, &b));
+  SapState& s = *c->sap;
   const double t0 = now_s();
-  // tables of the one right-hand side: time ratios, 4 + M, alpha
-  {
-    std::vector<double> rt(4 * g.T);
-    ratio_tables(g.T, c->bc_t, c->alpha.data(), rt.data());
-    DP_TRY(h2d(c, s.ratio.p, rt.data(), sizeof(double) * 4 * g.T));
-    const double m4 = 4.0 + c->M;
-    DP_TRY(h2d(c, s.m4.p, &m4, sizeof(double)));
-    DP_TRY(h2d(c, s.alpha.p, c->alpha.data(), sizeof(double) * g.T));
-  }
   // eta' = beta eta
   const size_t bytes = (size_t)2 * g.Vh * 12 * sizeof(double2);
   DP_HIP(c, c->scratch_aos.reserve(bytes));

@@ -51,3 +51,60 @@ def test_sap_rejects_bad_blocks():
             with pytest.raises(dp.DPError) as e:
                 L.solve_sap(eta, block)
             assert e.value.code == -1
+
+
+# One application of the preconditioner against the oracle's, element by
+# element.  Blocks of at most 256 sites run the fused kernel (one launch per
+# colour pass) with FP32 block solves; DP_SAP_FUSED=0 keeps the
+# launch-per-step path; FP64 block solves always take the latter.  The FP32
+# bound: each of the 5 x 2 passes rounds every residual and correction to
+# FP32 (2^-24 relative) through 4 minimal-residual steps with O(10)-term
+# sums, which stays within a few 1e-6 of the FP64 result in norm.
+@pytest.mark.parametrize("dims,block", [((8, 4, 8, 4), (4, 2, 4, 2)),   # 64-site blocks, 16 of them
+                                        ((8, 8, 8, 8), (4, 4, 4, 4)),   # 256 sites: every lane of the workgroup
+                                        ((4, 4, 4, 8), (2, 2, 2, 2)),   # 16 sites: most lanes idle
+                                        ((8, 6, 4, 4), (4, 3, 2, 2))])  # odd extent within a block
+@pytest.mark.parametrize("path", ["fused", "steps", "f64"])
+def test_sap_precondition_vs_oracle(dims, block, path, monkeypatch):
+    log(f"test_sap_precondition_vs_oracle {dims} {block} {path}")
+    monkeypatch.setenv("DP_SAP_FUSED", "0" if path == "steps" else "1")
+    U = synth.gauge_su3(dims, 0.4, 45)
+    C = oracle.clover(U, 1.6)
+    M = 0.05
+    beta = synth.beta_cosh_paper(dims, 0.3)
+    r = synth.random_spinor(dims, 46)
+    want = oracle.sap_apply(U, C, M, r, block, beta=beta)
+    with lattice(dims) as L:
+        L.set_gauge(U)
+        L.set_clover(1.6)
+        L.set_mass(M)
+        L.set_beta(beta)
+        got = L.sap_precondition(r, block, precision="f64" if path == "f64" else "f32")
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    worst = np.abs(got - want).max() / np.abs(want).max()
+    log(f"  relative error {err:.2e}, max {worst:.2e}")
+    if path == "f64":
+        assert err < 1e-12
+    else:
+        assert err < 1e-5 and worst < 1e-5
+
+
+def test_sap_fused_matches_steps(monkeypatch):
+    """The fused kernel and the launch-per-step path compute the same FP32
+    block solves in different orders: they agree to FP32 rounding."""
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    log("test_sap_fused_matches_steps")
+    U = synth.gauge_su3(dims, 0.4, 47)
+    r = synth.random_spinor(dims, 48)
+    out = {}
+    with lattice(dims) as L:
+        L.set_gauge(U)
+        L.set_clover(1.6)
+        L.set_mass(0.01)
+        L.set_beta(synth.beta_cosh_paper(dims, 0.2))
+        for path in ("1", "0"):
+            monkeypatch.setenv("DP_SAP_FUSED", path)
+            out[path] = L.sap_precondition(r, block, ncy=3, nmr=6)
+    err = np.linalg.norm(out["1"] - out["0"]) / np.linalg.norm(out["0"])
+    log(f"  fused vs steps {err:.2e}")
+    assert err < 1e-5
