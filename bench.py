@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--dslash-calls", type=int, default=200, help="timed operator calls per case")
     ap.add_argument("--sap-study", action="store_true",
                     help="SAP+GCR iteration counts vs alpha0 of the light-quark factorisation (one JSON line)")
+    ap.add_argument("--sap-workload", default=None, choices=["su3_24c48", "su3_32c64"],
+                    help="with --sap-study: only this lattice")
     ap.add_argument("--pmc-probe", action="store_true", help="run the counter probe (under rocprofv3 --pmc)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "ALG_JSON", "COMMAND"),
                     help="write the traffic record of the dominant kernel from two counter runs")
@@ -201,7 +203,7 @@ def main():
     if args.pmc_summary:
         return pmc_summary(*args.pmc_summary)
     if args.sap_study:
-        return sap_study()
+        return sap_study(args.sap_workload)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (one process drives one GPU)",
               file=sys.stderr)
@@ -389,7 +391,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def sap_study():
+def sap_study(only=None):
     """The analogue of the paper's Table 1 on the synthetic fields: SAP+GCR
     iterations (and seconds) to invert the light-quark Dirac equation with the
     four-direction cosh factorisation (eq. betaa) for alpha0 in {0, 0.2, 0.4};
@@ -400,6 +402,8 @@ def sap_study():
     import synth
     out = []
     for name, block, r in (("su3_24c48", (6, 6, 6, 6), 1e-11), ("su3_32c64", (4, 4, 4, 4), 1e-10)):
+        if only and name != only:
+            continue
         cfg = synth.config(name)
         dims = cfg["dims"]
         U = synth.gauge_su3(dims, cfg["eps"], cfg["seed"])

@@ -386,6 +386,30 @@ __device__ __forceinline__ void bl_link(const cx<float> (&u)[9], const cx<float>
     }
 }
 
+// y = (C + m4) x with the site's clover blocks read from the block layout,
+// one chirality at a time
+__device__ __forceinline__ void bl_diag(const float4* C, int blk, int vol, int s, float m4, const cx<float> (&x)[12],
+                                        cx<float> (&y)[12]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float raw[36];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const float4 v = C[((long)blk * 18 + 9 * h + q) * vol + s];
+      raw[4 * q] = v.x;
+      raw[4 * q + 1] = v.y;
+      raw[4 * q + 2] = v.z;
+      raw[4 * q + 3] = v.w;
+    }
+    HermBlock<float> B;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) B.d[q] = raw[q];
+#pragma unroll
+    for (int q = 0; q < 15; ++q) B.o[q] = cx<float>{raw[6 + 2 * q], raw[7 + 2 * q]};
+    herm_apply(B, m4, &x[6 * h], &y[6 * h]);
+  }
+}
+
 __device__ __forceinline__ void bl_load_spinor(const float4* f, long base, int vol, int s, cx<float> (&v)[12]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
@@ -405,140 +429,204 @@ struct SapPass {
   float4* psi;
   const float2* U;
   const float4* C;
+  float4* av;            // the large-block kernel's D'_B rho between its two phases (block layout)
   const double* rt;      // time hop ratios [4][T] (fwd, bwd, ...; boundary sign folded in)
   const double* sratio;  // spatial hop ratios of the light-quark factorisation, or null
   float m4;              // 4 + M
 };
 
+// the origin of the kidx-th block of a colour
+__device__ __forceinline__ void bl_origin(const Blocking& b, int colour, int kidx, int (&o)[4]) {
+  const int h3 = b.nb[3] / 2;
+  int c3 = kidx % h3;
+  kidx /= h3;
+  const int c2 = kidx % b.nb[2];
+  kidx /= b.nb[2];
+  const int c1 = kidx % b.nb[1];
+  const int c0 = kidx / b.nb[1];
+  c3 = 2 * c3 + ((colour + c0 + c1 + c2) & 1);
+  o[0] = c0 * b.bs[0];
+  o[1] = c1 * b.bs[1];
+  o[2] = c2 * b.bs[2];
+  o[3] = c3 * b.bs[3];
+}
+
+// coordinates within its block of the block's site s
+__device__ __forceinline__ void bl_local(const Blocking& b, int s, int (&l)[4]) {
+  l[3] = s % b.bs[3];
+  s /= b.bs[3];
+  l[2] = s % b.bs[2];
+  s /= b.bs[2];
+  l[1] = s % b.bs[1];
+  l[0] = s / b.bs[1];
+}
+
+// hop coefficients at x: time ratios, spatial ratios (or 1)
+__device__ __forceinline__ void bl_coefs(const SapPass& a, const int (&x)[4], float (&cf)[4], float (&cb)[4]) {
+  const Geom& g = a.g;
+  const int Ls[4] = {g.T, g.L1, g.L2, g.L3};
+  cf[0] = (float)a.rt[x[0]];
+  cb[0] = (float)a.rt[g.T + x[0]];
+  int off = 0;
+#pragma unroll
+  for (int mu = 1; mu < 4; ++mu) {
+    cf[mu] = a.sratio ? (float)a.sratio[off + x[mu]] : 1.f;
+    cb[mu] = a.sratio ? (float)a.sratio[off + Ls[mu] + x[mu]] : 1.f;
+    off += 4 * Ls[mu];
+  }
+}
+
+__device__ __forceinline__ void bl_load_link(const float2* U, int blk, int mu, int vol, int s, cx<float> (&u)[9]) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const float2 v = U[((long)blk * 36 + mu * 9 + q) * vol + s];
+    u[q] = cx<float>{v.x, v.y};
+  }
+}
+
+// out = D' psi at site x (site s of block blk), psi from memory, every
+// neighbour inside or outside the block; with own_zero the psi of block blk is
+// zero and not read.  REG: the site's forward links are Ureg.
+template <bool REG, int MU>
+__device__ __forceinline__ void bl_dprime_dir(const SapPass& a, int blk, const int (&x)[4], float cfm, float cbm,
+                                              const cx<float> (&Ureg)[4][9], int s, cx<float> (&out)[12]) {
+  const Geom& g = a.g;
+  const Blocking& b = a.b;
+  const int L = MU == 0 ? g.T : MU == 1 ? g.L1 : MU == 2 ? g.L2 : g.L3;
+  cx<float> v[12], h[6], w[6], u[9];
+  int y[4] = {x[0], x[1], x[2], x[3]};
+  y[MU] = x[MU] + 1 == L ? 0 : x[MU] + 1;
+  BLoc q = bl_locate(b, y[0], y[1], y[2], y[3]);
+  if (!(a.own_zero && q.blk == blk)) {
+    bl_load_spinor(a.psi, (long)q.blk * 6, b.vol, q.s, v);
+    bl_proj<MU, 1>(v, h);
+    if constexpr (REG) {
+      bl_link<false>(Ureg[MU], h, w);
+    } else {
+      bl_load_link(a.U, blk, MU, b.vol, s, u);
+      bl_link<false>(u, h, w);
+    }
+    bl_recon<MU, 1>(out, w, -0.5f * cfm);
+  }
+  y[MU] = x[MU] == 0 ? L - 1 : x[MU] - 1;
+  q = bl_locate(b, y[0], y[1], y[2], y[3]);
+  if (!(a.own_zero && q.blk == blk)) {
+    bl_load_link(a.U, q.blk, MU, b.vol, q.s, u);
+    bl_load_spinor(a.psi, (long)q.blk * 6, b.vol, q.s, v);
+    bl_proj<MU, -1>(v, h);
+    bl_link<true>(u, h, w);
+    bl_recon<MU, -1>(out, w, -0.5f * cbm);
+  }
+}
+
+template <bool REG>
+__device__ __forceinline__ void bl_dprime(const SapPass& a, int blk, int s, const int (&x)[4], const float (&cf)[4],
+                                          const float (&cb)[4], const cx<float> (&Ureg)[4][9],
+                                          cx<float> (&out)[12]) {
+  if (!a.own_zero) {
+    cx<float> v[12];
+    bl_load_spinor(a.psi, (long)blk * 6, a.b.vol, s, v);
+    bl_diag(a.C, blk, a.b.vol, s, a.m4, v, out);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[c] = cx<float>{0.f, 0.f};
+  }
+  bl_dprime_dir<REG, 0>(a, blk, x, cf[0], cb[0], Ureg, s, out);
+  bl_dprime_dir<REG, 1>(a, blk, x, cf[1], cb[1], Ureg, s, out);
+  bl_dprime_dir<REG, 2>(a, blk, x, cf[2], cb[2], Ureg, s, out);
+  bl_dprime_dir<REG, 3>(a, blk, x, cf[3], cb[3], Ureg, s, out);
+}
+
+// the minimal-residual coefficient w = <a, rho>_B / |a|^2_B from per-thread
+// FP64 partials: wave sums, then the waves in order (every thread calls it)
+template <int NT>
+__device__ __forceinline__ cx<float> bl_mr_coef(double nr, double ni, double dn, double (&red)[3][NT / 64],
+                                                double (&wsh)[2]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  nr = wave_sum(nr);
+  ni = wave_sum(ni);
+  dn = wave_sum(dn);
+  if (lane == 0) {
+    red[0][wv] = nr;
+    red[1][wv] = ni;
+    red[2][wv] = dn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sr = 0.0, si = 0.0, sd = 0.0;
+    for (int q = 0; q < NT / 64; ++q) {
+      sr += red[0][q];
+      si += red[1][q];
+      sd += red[2][q];
+    }
+    wsh[0] = sd > 0.0 ? sr / sd : 0.0;
+    wsh[1] = sd > 0.0 ? si / sd : 0.0;
+  }
+  __syncthreads();
+  return cx<float>{(float)wsh[0], (float)wsh[1]};
+}
+
+__device__ __forceinline__ void bl_mr_sums(const cx<float> (&av)[12], const cx<float> (&rv)[12], double& nr,
+                                           double& ni, double& dn) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    nr += (double)av[c].x * (double)rv[c].x + (double)av[c].y * (double)rv[c].y;
+    ni += (double)av[c].x * (double)rv[c].y - (double)av[c].y * (double)rv[c].x;
+    dn += (double)av[c].x * (double)av[c].x + (double)av[c].y * (double)av[c].y;
+  }
+}
+
+__device__ __forceinline__ void bl_store_psi(const SapPass& a, int blk, int s, const cx<float> (&dpsi)[12]) {
+  cx<float> v[12];
+  if (a.own_zero) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = dpsi[c];
+  } else {
+    bl_load_spinor(a.psi, (long)blk * 6, a.b.vol, s, v);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = v[c] + dpsi[c];
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+    a.psi[((long)blk * 6 + q) * a.b.vol + s] = make_float4(v[2 * q].x, v[2 * q].y, v[2 * q + 1].x, v[2 * q + 1].y);
+}
+
 // One pass of the Schwarz procedure over the blocks of one colour:
 // rho = r - D' psi on the block (NB_ZERO: psi = 0 everywhere, rho = r), nmr
 // minimal-residual steps with the Dirichlet block operator, psi += the
 // accumulated correction.  Block sums in FP64, reduced in a fixed order.
+// Blocks of at most kSapThreads sites, a thread per site.
 template <bool NB_ZERO>
-__global__ void __launch_bounds__(kSapThreads) sap_block_kernel(SapPass a) {
+__global__ void __launch_bounds__(kSapThreads, 2) sap_block_kernel(SapPass a) {
   __shared__ float rho_l[24 * kSapThreads];
   __shared__ float hb[4 * 12 * kSapThreads];  // backward hops handed to x + mu
   __shared__ double red[3][kSapThreads / 64];
   __shared__ double wsh[2];
-  const Geom& g = a.g;
   const Blocking& b = a.b;
   const int s = threadIdx.x;
   const bool valid = s < b.vol;
-  // the blockIdx.x-th block of the colour
-  int k = blockIdx.x;
-  const int h3 = b.nb[3] / 2;
-  int c3 = k % h3;
-  k /= h3;
-  const int c2 = k % b.nb[2];
-  k /= b.nb[2];
-  const int c1 = k % b.nb[1];
-  const int c0 = k / b.nb[1];
-  c3 = 2 * c3 + ((a.colour + c0 + c1 + c2) & 1);
   const int blk = a.colour * b.nhalf + blockIdx.x;
   const int st[4] = {b.bs[1] * b.bs[2] * b.bs[3], b.bs[2] * b.bs[3], b.bs[3], 1};
-  int l[4];
-  {
-    int t = valid ? s : 0;
-    l[3] = t % b.bs[3];
-    t /= b.bs[3];
-    l[2] = t % b.bs[2];
-    t /= b.bs[2];
-    l[1] = t % b.bs[1];
-    l[0] = t / b.bs[1];
-  }
-  const int x[4] = {c0 * b.bs[0] + l[0], c1 * b.bs[1] + l[1], c2 * b.bs[2] + l[2], c3 * b.bs[3] + l[3]};
-  const int Ls[4] = {g.T, g.L1, g.L2, g.L3};
-  // hop coefficients: time ratios, spatial ratios (or 1)
+  int o[4], l[4];
+  bl_origin(b, a.colour, blockIdx.x, o);
+  bl_local(b, valid ? s : 0, l);
+  const int x[4] = {o[0] + l[0], o[1] + l[1], o[2] + l[2], o[3] + l[3]};
   float cf[4], cb[4];
-  cf[0] = (float)a.rt[x[0]];
-  cb[0] = (float)a.rt[g.T + x[0]];
-  {
-    int off = 0;
-#pragma unroll
-    for (int mu = 1; mu < 4; ++mu) {
-      cf[mu] = a.sratio ? (float)a.sratio[off + x[mu]] : 1.f;
-      cb[mu] = a.sratio ? (float)a.sratio[off + Ls[mu] + x[mu]] : 1.f;
-      off += 4 * Ls[mu];
-    }
-  }
-  // the site's forward links and clover blocks, kept for the pass
+  bl_coefs(a, x, cf, cb);
+  // the site's forward links, kept for the pass (the clover blocks are
+  // read again at each use: holding them too would halve the waves per SIMD)
   cx<float> U[4][9];
-  HermBlock<float> B[2];
-  {
-    const long ub = (long)blk * 36;
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const float2 v = a.U[(ub + mu * 9 + q) * b.vol + s * valid];
-        U[mu][q] = cx<float>{v.x, v.y};
-      }
-    float raw[72];
-#pragma unroll
-    for (int q = 0; q < 18; ++q) {
-      const float4 v = a.C[((long)blk * 18 + q) * b.vol + s * valid];
-      raw[4 * q] = v.x;
-      raw[4 * q + 1] = v.y;
-      raw[4 * q + 2] = v.z;
-      raw[4 * q + 3] = v.w;
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-#pragma unroll
-      for (int q = 0; q < 6; ++q) B[h].d[q] = raw[36 * h + q];
-#pragma unroll
-      for (int q = 0; q < 15; ++q) B[h].o[q] = cx<float>{raw[36 * h + 6 + 2 * q], raw[36 * h + 7 + 2 * q]};
-    }
-  }
+  for (int mu = 0; mu < 4; ++mu) bl_load_link(a.U, blk, mu, b.vol, valid ? s : 0, U[mu]);
   // block residual
   if (valid) {
     cx<float> rv[12];
     bl_load_spinor(a.r, (long)blk * 6, b.vol, s, rv);
     if constexpr (!NB_ZERO) {
-      cx<float> acc[12], out[12], v[12], h[6], w[6];
+      cx<float> out[12];
+      bl_dprime<true>(a, blk, s, x, cf, cb, U, out);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        acc[c] = cx<float>{0.f, 0.f};
-        out[c] = cx<float>{0.f, 0.f};
-      }
-      if (!a.own_zero) {
-        bl_load_spinor(a.psi, (long)blk * 6, b.vol, s, v);
-        herm_apply(B[0], a.m4, &v[0], &out[0]);
-        herm_apply(B[1], a.m4, &v[6], &out[6]);
-      }
-      // the eight neighbours, inside or outside the block
-#define DP_SAP_RES_DIR(MU)                                                                         \
-  {                                                                                                \
-    int y[4] = {x[0], x[1], x[2], x[3]};                                                           \
-    y[MU] = x[MU] + 1 == Ls[MU] ? 0 : x[MU] + 1;                                                   \
-    BLoc q = bl_locate(b, y[0], y[1], y[2], y[3]);                                                 \
-    if (!(a.own_zero && q.blk == blk)) {                                                           \
-      bl_load_spinor(a.psi, (long)q.blk * 6, b.vol, q.s, v);                                       \
-      bl_proj<MU, 1>(v, h);                                                                        \
-      bl_link<false>(U[MU], h, w);                                                                 \
-      bl_recon<MU, 1>(acc, w, cf[MU]);                                                             \
-    }                                                                                              \
-    y[MU] = x[MU] == 0 ? Ls[MU] - 1 : x[MU] - 1;                                                   \
-    q = bl_locate(b, y[0], y[1], y[2], y[3]);                                                      \
-    if (!(a.own_zero && q.blk == blk)) {                                                           \
-      cx<float> ub[9];                                                                             \
-      for (int e = 0; e < 9; ++e) {                                                                \
-        const float2 t = a.U[((long)q.blk * 36 + MU * 9 + e) * b.vol + q.s];                       \
-        ub[e] = cx<float>{t.x, t.y};                                                               \
-      }                                                                                            \
-      bl_load_spinor(a.psi, (long)q.blk * 6, b.vol, q.s, v);                                       \
-      bl_proj<MU, -1>(v, h);                                                                       \
-      bl_link<true>(ub, h, w);                                                                     \
-      bl_recon<MU, -1>(acc, w, cb[MU]);                                                            \
-    }                                                                                              \
-  }
-      DP_SAP_RES_DIR(0)
-      DP_SAP_RES_DIR(1)
-      DP_SAP_RES_DIR(2)
-      DP_SAP_RES_DIR(3)
-#undef DP_SAP_RES_DIR
-#pragma unroll
-      for (int c = 0; c < 12; ++c) rv[c] = rv[c] - (out[c] + (-0.5f) * acc[c]);
+      for (int c = 0; c < 12; ++c) rv[c] = rv[c] - out[c];
     }
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
@@ -549,23 +637,23 @@ __global__ void __launch_bounds__(kSapThreads) sap_block_kernel(SapPass a) {
   cx<float> dpsi[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) dpsi[c] = cx<float>{0.f, 0.f};
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int it = 0; it < a.nmr; ++it) {
     __syncthreads();  // rho complete
     cx<float> rv[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) rv[c] = cx<float>{rho_l[(2 * c) * kSapThreads + s], rho_l[(2 * c + 1) * kSapThreads + s]};
+    for (int c = 0; c < 12; ++c)
+      rv[c] = cx<float>{rho_l[(2 * c) * kSapThreads + s], rho_l[(2 * c + 1) * kSapThreads + s]};
     // hand the backward hops to the sites x + mu of the block
     if (valid) {
       cx<float> h[6], w[6];
-#define DP_SAP_PUSH(MU)                                                       \
-  if (l[MU] + 1 < b.bs[MU]) {                                                 \
-    bl_proj<MU, -1>(rv, h);                                                   \
-    bl_link<true>(U[MU], h, w);                                               \
-    for (int e = 0; e < 6; ++e) {                                             \
-      hb[((MU * 12) + 2 * e) * kSapThreads + s + st[MU]] = w[e].x;            \
-      hb[((MU * 12) + 2 * e + 1) * kSapThreads + s + st[MU]] = w[e].y;        \
-    }                                                                         \
+#define DP_SAP_PUSH(MU)                                                \
+  if (l[MU] + 1 < b.bs[MU]) {                                          \
+    bl_proj<MU, -1>(rv, h);                                            \
+    bl_link<true>(U[MU], h, w);                                        \
+    for (int e = 0; e < 6; ++e) {                                      \
+      hb[((MU * 12) + 2 * e) * kSapThreads + s + st[MU]] = w[e].x;     \
+      hb[((MU * 12) + 2 * e + 1) * kSapThreads + s + st[MU]] = w[e].y; \
+    }                                                                  \
   }
       DP_SAP_PUSH(0)
       DP_SAP_PUSH(1)
@@ -574,64 +662,36 @@ __global__ void __launch_bounds__(kSapThreads) sap_block_kernel(SapPass a) {
 #undef DP_SAP_PUSH
     }
     __syncthreads();
-    // av = D'_B rho at x
+    // av = D'_B rho at x: the diagonal term, then the hops with -1/2 folded
+    // into their coefficients
     cx<float> av[12];
     double nr = 0.0, ni = 0.0, dn = 0.0;
     if (valid) {
-      cx<float> acc[12], v[12], h[6], w[6];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) acc[c] = cx<float>{0.f, 0.f};
-#define DP_SAP_PULL(MU)                                                                                      \
-  if (l[MU] + 1 < b.bs[MU]) {                                                                                \
-    const int n = s + st[MU];                                                                                \
-    for (int c = 0; c < 12; ++c) v[c] = cx<float>{rho_l[(2 * c) * kSapThreads + n], rho_l[(2 * c + 1) * kSapThreads + n]}; \
-    bl_proj<MU, 1>(v, h);                                                                                    \
-    bl_link<false>(U[MU], h, w);                                                                             \
-    bl_recon<MU, 1>(acc, w, cf[MU]);                                                                         \
-  }                                                                                                          \
-  if (l[MU] > 0) {                                                                                           \
-    for (int e = 0; e < 6; ++e)                                                                              \
+      cx<float> v[12], h[6], w[6];
+      bl_diag(a.C, blk, b.vol, s, a.m4, rv, av);
+#define DP_SAP_PULL(MU)                                                                                 \
+  if (l[MU] + 1 < b.bs[MU]) {                                                                           \
+    const int n = s + st[MU];                                                                           \
+    for (int c = 0; c < 12; ++c)                                                                        \
+      v[c] = cx<float>{rho_l[(2 * c) * kSapThreads + n], rho_l[(2 * c + 1) * kSapThreads + n]};         \
+    bl_proj<MU, 1>(v, h);                                                                               \
+    bl_link<false>(U[MU], h, w);                                                                        \
+    bl_recon<MU, 1>(av, w, -0.5f * cf[MU]);                                                             \
+  }                                                                                                     \
+  if (l[MU] > 0) {                                                                                      \
+    for (int e = 0; e < 6; ++e)                                                                         \
       w[e] = cx<float>{hb[((MU * 12) + 2 * e) * kSapThreads + s], hb[((MU * 12) + 2 * e + 1) * kSapThreads + s]}; \
-    bl_recon<MU, -1>(acc, w, cb[MU]);                                                                        \
+    bl_recon<MU, -1>(av, w, -0.5f * cb[MU]);                                                            \
   }
       DP_SAP_PULL(0)
       DP_SAP_PULL(1)
       DP_SAP_PULL(2)
       DP_SAP_PULL(3)
 #undef DP_SAP_PULL
-      herm_apply(B[0], a.m4, &rv[0], &av[0]);
-      herm_apply(B[1], a.m4, &rv[6], &av[6]);
-#pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        av[c] = av[c] + (-0.5f) * acc[c];
-        nr += (double)av[c].x * (double)rv[c].x + (double)av[c].y * (double)rv[c].y;
-        ni += (double)av[c].x * (double)rv[c].y - (double)av[c].y * (double)rv[c].x;
-        dn += (double)av[c].x * (double)av[c].x + (double)av[c].y * (double)av[c].y;
-      }
+      bl_mr_sums(av, rv, nr, ni, dn);
     }
-    // w = <a, rho>_B / |a|^2_B
-    nr = wave_sum(nr);
-    ni = wave_sum(ni);
-    dn = wave_sum(dn);
-    if (lane == 0) {
-      red[0][wv] = nr;
-      red[1][wv] = ni;
-      red[2][wv] = dn;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double sr = 0.0, si = 0.0, sd = 0.0;
-      for (int q = 0; q < kSapThreads / 64; ++q) {
-        sr += red[0][q];
-        si += red[1][q];
-        sd += red[2][q];
-      }
-      wsh[0] = sd > 0.0 ? sr / sd : 0.0;
-      wsh[1] = sd > 0.0 ? si / sd : 0.0;
-    }
-    __syncthreads();
+    const cx<float> w = bl_mr_coef<kSapThreads>(nr, ni, dn, red, wsh);
     if (valid) {
-      const cx<float> w{(float)wsh[0], (float)wsh[1]};
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         dpsi[c] = dpsi[c] + cmul(w, rv[c]);
@@ -641,23 +701,180 @@ __global__ void __launch_bounds__(kSapThreads) sap_block_kernel(SapPass a) {
       }
     }
   }
-  if (valid) {
-    cx<float> v[12];
-    if (a.own_zero) {
+  if (valid) bl_store_psi(a, blk, s, dpsi);
+}
+
+// The same pass for blocks of kSapThreads + 1 .. kSapBigSites sites:
+// kSapBigThreads threads with kSapBigPer sites each (site s = thread + q
+// kSapBigThreads); the residual in LDS as before, but the links are read at
+// each use, both hops of a site read rho from LDS (no hand-over buffer), and
+// D'_B rho and psi stay in memory between the phases of a step, so that a
+// block of up to 1536 sites fits.
+constexpr int kSapBigThreads = 512;
+constexpr int kSapBigPer = 3;
+constexpr int kSapBigSites = kSapBigThreads * kSapBigPer;
+
+template <bool NB_ZERO>
+__global__ void __launch_bounds__(kSapBigThreads, 2) sap_block_big_kernel(SapPass a) {
+  __shared__ float rho_l[24 * kSapBigSites];
+  __shared__ double red[3][kSapBigThreads / 64];
+  __shared__ double wsh[2];
+  const Blocking& b = a.b;
+  const int blk = a.colour * b.nhalf + blockIdx.x;
+  const int st[4] = {b.bs[1] * b.bs[2] * b.bs[3], b.bs[2] * b.bs[3], b.bs[3], 1};
+  int o[4];
+  bl_origin(b, a.colour, blockIdx.x, o);
+  const cx<float> Unone[4][9] = {};
+  // block residual
+#pragma unroll 1
+  for (int q = 0; q < kSapBigPer; ++q) {
+    const int s = threadIdx.x + q * kSapBigThreads;
+    if (s < b.vol) {
+      int l[4];
+      bl_local(b, s, l);
+      const int x[4] = {o[0] + l[0], o[1] + l[1], o[2] + l[2], o[3] + l[3]};
+      cx<float> rv[12];
+      bl_load_spinor(a.r, (long)blk * 6, b.vol, s, rv);
+      if constexpr (!NB_ZERO) {
+        float cf[4], cb[4];
+        bl_coefs(a, x, cf, cb);
+        cx<float> out[12];
+        bl_dprime<false>(a, blk, s, x, cf, cb, Unone, out);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) v[c] = dpsi[c];
-    } else {
-      bl_load_spinor(a.psi, (long)blk * 6, b.vol, s, v);
+        for (int c = 0; c < 12; ++c) rv[c] = rv[c] - out[c];
+      }
 #pragma unroll
-      for (int c = 0; c < 12; ++c) v[c] = v[c] + dpsi[c];
+      for (int c = 0; c < 12; ++c) {
+        rho_l[(2 * c) * kSapBigSites + s] = rv[c].x;
+        rho_l[(2 * c + 1) * kSapBigSites + s] = rv[c].y;
+      }
     }
+  }
+  for (int it = 0; it < a.nmr; ++it) {
+    __syncthreads();  // rho complete
+    double nr = 0.0, ni = 0.0, dn = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < kSapBigPer; ++q) {
+      const int s = threadIdx.x + q * kSapBigThreads;
+      if (s < b.vol) {
+        int l[4];
+        bl_local(b, s, l);
+        const int x[4] = {o[0] + l[0], o[1] + l[1], o[2] + l[2], o[3] + l[3]};
+        float cf[4], cb[4];
+        bl_coefs(a, x, cf, cb);
+        cx<float> rv[12], av[12], v[12], h[6], w[6], u[9];
 #pragma unroll
-    for (int q = 0; q < 6; ++q)
-      a.psi[((long)blk * 6 + q) * b.vol + s] = make_float4(v[2 * q].x, v[2 * q].y, v[2 * q + 1].x, v[2 * q + 1].y);
+        for (int c = 0; c < 12; ++c)
+          rv[c] = cx<float>{rho_l[(2 * c) * kSapBigSites + s], rho_l[(2 * c + 1) * kSapBigSites + s]};
+        bl_diag(a.C, blk, b.vol, s, a.m4, rv, av);
+#define DP_SAP_BIG(MU)                                                                                   \
+  if (l[MU] + 1 < b.bs[MU]) {                                                                            \
+    const int n = s + st[MU];                                                                            \
+    for (int c = 0; c < 12; ++c)                                                                         \
+      v[c] = cx<float>{rho_l[(2 * c) * kSapBigSites + n], rho_l[(2 * c + 1) * kSapBigSites + n]};        \
+    bl_proj<MU, 1>(v, h);                                                                                \
+    bl_load_link(a.U, blk, MU, b.vol, s, u);                                                             \
+    bl_link<false>(u, h, w);                                                                             \
+    bl_recon<MU, 1>(av, w, -0.5f * cf[MU]);                                                              \
+  }                                                                                                      \
+  if (l[MU] > 0) {                                                                                       \
+    const int n = s - st[MU];                                                                            \
+    for (int c = 0; c < 12; ++c)                                                                         \
+      v[c] = cx<float>{rho_l[(2 * c) * kSapBigSites + n], rho_l[(2 * c + 1) * kSapBigSites + n]};        \
+    bl_proj<MU, -1>(v, h);                                                                               \
+    bl_load_link(a.U, blk, MU, b.vol, n, u);                                                             \
+    bl_link<true>(u, h, w);                                                                              \
+    bl_recon<MU, -1>(av, w, -0.5f * cb[MU]);                                                             \
+  }
+        DP_SAP_BIG(0)
+        DP_SAP_BIG(1)
+        DP_SAP_BIG(2)
+        DP_SAP_BIG(3)
+#undef DP_SAP_BIG
+        bl_mr_sums(av, rv, nr, ni, dn);
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+          a.av[((long)blk * 6 + e) * b.vol + s] = make_float4(av[2 * e].x, av[2 * e].y, av[2 * e + 1].x, av[2 * e + 1].y);
+      }
+    }
+    const cx<float> w = bl_mr_coef<kSapBigThreads>(nr, ni, dn, red, wsh);
+#pragma unroll 1
+    for (int q = 0; q < kSapBigPer; ++q) {
+      const int s = threadIdx.x + q * kSapBigThreads;
+      if (s < b.vol) {
+        cx<float> rv[12], dp[12], av[12];
+        bl_load_spinor(a.av, (long)blk * 6, b.vol, s, av);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          rv[c] = cx<float>{rho_l[(2 * c) * kSapBigSites + s], rho_l[(2 * c + 1) * kSapBigSites + s]};
+          dp[c] = cmul(w, rv[c]);
+          rv[c] = rv[c] - cmul(w, av[c]);
+          rho_l[(2 * c) * kSapBigSites + s] = rv[c].x;
+          rho_l[(2 * c + 1) * kSapBigSites + s] = rv[c].y;
+        }
+        // psi += w rho (psi of the block is read only by this workgroup)
+        if (!(a.own_zero && it == 0)) {
+          cx<float> pv[12];
+          bl_load_spinor(a.psi, (long)blk * 6, b.vol, s, pv);
+#pragma unroll
+          for (int c = 0; c < 12; ++c) dp[c] = pv[c] + dp[c];
+        }
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+          a.psi[((long)blk * 6 + e) * b.vol + s] = make_float4(dp[2 * e].x, dp[2 * e].y, dp[2 * e + 1].x, dp[2 * e + 1].y);
+      }
+    }
   }
 }
 
 constexpr int kDotBlocks = 1024;
+
+// The sum of the block partials of vec_dot_kernel in block order (the order
+// the host used), on the device: out = <x, y> (mode 0), out = (|x|, 0)
+// (mode 1), or <x, y> unless guard[0] (a norm) is zero or not finite, then 0
+// (mode 2).
+__global__ void __launch_bounds__(64) dot_finish_kernel(const double* __restrict__ partials, int mode,
+                                                        const double* __restrict__ guard, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double re = 0.0, im = 0.0;
+  for (int k = 0; k < kDotBlocks; ++k) {
+    re += partials[2 * k];
+    im += partials[2 * k + 1];
+  }
+  if (mode == 1) {
+    re = sqrt(re);
+    im = 0.0;
+  } else if (mode == 2 && !(guard[0] > 0.0 && isfinite(guard[0]))) {
+    re = im = 0.0;
+  }
+  out[0] = re;
+  out[1] = im;
+}
+
+// vec_update_kernel with its coefficient on the device: op 0: y += sgn coef x
+// (coef complex); op 1: y = y / coef[0] (a norm; y is left alone when it is
+// zero or not finite)
+__global__ void __launch_bounds__(kBlock) vec_update_dev_kernel(Geom g, int op, const double* __restrict__ coef,
+                                                                double sgn, SpinorRef x, SpinorRef y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (i >= g.Vh) return;
+  const double c0 = coef[0], c1 = coef[1];
+  if (op == 1 && !(c0 > 0.0 && isfinite(c0))) return;
+  cx<double> vx[12], vy[12];
+  SpinorIO<F64>::load(y, p, i, g.Vp, vy);
+  if (op == 0) {
+    SpinorIO<F64>::load(x, p, i, g.Vp, vx);
+    const cx<double> a{sgn * c0, sgn * c1};
+#pragma unroll
+    for (int c = 0; c < 12; ++c) vy[c] = vy[c] + cmul(a, vx[c]);
+  } else {
+    const double ar = 1.0 / c0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) vy[c] = ar * vy[c];
+  }
+  SpinorIO<F64>::store(y, p, i, g.Vp, vy);
+}
 
 }  // namespace
 
@@ -671,15 +888,25 @@ struct SapState {
   std::vector<Field> z, w;  // FP64, nkv each
   Field q_r, q_psi, q_rho, q_a;  // block-solve precision
   DevBuf ratio, m4, partials, alpha, cpp;
+  // GCR coefficients on the device: c_jk [nkv][nkv], gamma_k [nkv], b_k
+  // [nkv] (complex pairs), |r|^2; and their host copy
+  DevBuf gcr;
+  std::vector<double> h_gcr;
   // fused block solves: links, clover, r and psi in block layout (FP32)
   bool fused = false;
-  DevBuf ubl, cbl, rbl, pbl;
+  DevBuf ubl, cbl, rbl, pbl, abl;
   std::vector<double> h_part;
 };
 
 namespace {
 
 using zc = std::complex<double>;
+
+size_t gcr_len(int nkv) { return (size_t)2 * nkv * nkv + 4 * nkv + 2; }
+size_t gcr_cc(int nkv, int j, int k) { return (size_t)2 * (j * nkv + k); }
+size_t gcr_gam(int nkv, int k) { return (size_t)2 * nkv * nkv + 2 * k; }
+size_t gcr_bn(int nkv, int k) { return (size_t)2 * nkv * nkv + 2 * nkv + 2 * k; }
+size_t gcr_rn(int nkv) { return (size_t)2 * nkv * nkv + 4 * nkv; }
 
 int sap_alloc(dp_ctx* c, SapState& s, int nkv, int prec) {
   const Geom& g = c->g;
@@ -699,6 +926,8 @@ int sap_alloc(dp_ctx* c, SapState& s, int nkv, int prec) {
   DP_HIP(c, s.m4.reserve(sizeof(double)));
   DP_HIP(c, s.alpha.reserve(sizeof(double) * g.T));
   DP_HIP(c, s.partials.reserve(sizeof(double) * 2 * kDotBlocks));
+  s.h_gcr.resize(gcr_len(nkv));
+  DP_HIP(c, s.gcr.reserve(sizeof(double) * s.h_gcr.size()));
   s.h_part.resize(2 * kDotBlocks);
   s.g = g;
   s.nkv = nkv;
@@ -761,6 +990,23 @@ int vec_dot(dp_ctx* c, SapState& s, const Field& x, const Field& y, zc* out) {
   return DP_OK;
 }
 
+// out = the finished <x, y> on the device (dot_finish_kernel's mode)
+int vec_dot_dev(dp_ctx* c, SapState& s, const Field& x, const Field& y, int mode, const double* guard, double* out) {
+  hipLaunchKernelGGL(vec_dot_kernel, dim3(kDotBlocks), dim3(kBlock), 0, c->stream, c->g, x.ref(), y.ref(),
+                     s.partials.as<double>());
+  DP_HIP(c, hipGetLastError());
+  hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(64), 0, c->stream, s.partials.as<double>(), mode, guard, out);
+  DP_HIP(c, hipGetLastError());
+  return DP_OK;
+}
+
+int vec_update_dev(dp_ctx* c, int op, const double* coef, double sgn, const Field& x, const Field& y) {
+  hipLaunchKernelGGL(vec_update_dev_kernel, site_grid(c->g), dim3(kBlock), 0, c->stream, c->g, op, coef, sgn,
+                     x.ref(), y.ref());
+  DP_HIP(c, hipGetLastError());
+  return DP_OK;
+}
+
 template <int PI, int PO>
 int convert(dp_ctx* c, const Field& x, const Field& y) {
   hipLaunchKernelGGL((vec_convert_kernel<PI, PO>), site_grid(c->g), dim3(kBlock), 0, c->stream, c->g, x.ref(),
@@ -796,9 +1042,9 @@ int sap_apply(dp_ctx* c, SapState& s, const Blocking& b, int ncy, int nmr) {
 }
 
 // The fused block solves take FP32 block solves on blocks of at most
-// kSapThreads sites (DP_SAP_FUSED=0 keeps the launch-per-step path).
+// kSapBigSites sites (DP_SAP_FUSED=0 keeps the launch-per-step path).
 bool sap_fused_enabled(int prec, const Blocking& b) {
-  if (prec != F32 || b.vol > kSapThreads) return false;
+  if (prec != F32 || b.vol > kSapBigSites) return false;
   const char* e = std::getenv("DP_SAP_FUSED");
   return !(e && e[0] == '0');
 }
@@ -810,6 +1056,7 @@ int sap_fused_setup(dp_ctx* c, SapState& s, const Blocking& b) {
   DP_HIP(c, s.cbl.reserve(sizeof(float4) * 18 * V));
   DP_HIP(c, s.rbl.reserve(sizeof(float4) * 6 * V));
   DP_HIP(c, s.pbl.reserve(sizeof(float4) * 6 * V));
+  if (b.vol > kSapThreads) DP_HIP(c, s.abl.reserve(sizeof(float4) * 6 * V));
   hipLaunchKernelGGL(sap_gather_kernel, site_grid(c->g), dim3(kBlock), 0, c->stream, c->g, b,
                      c->U[F32][0].as<float2>(), c->U[F32][1].as<float2>(), c->C32[0].as<float4>(),
                      c->C32[1].as<float4>(), s.ubl.as<float2>(), s.cbl.as<float4>());
@@ -827,6 +1074,7 @@ int sap_apply_fused(dp_ctx* c, SapState& s, const Blocking& b, int ncy, int nmr)
   a.psi = s.pbl.as<float4>();
   a.U = s.ubl.as<float2>();
   a.C = s.cbl.as<float4>();
+  a.av = s.abl.as<float4>();
   a.rt = s.ratio.as<double>();
   a.sratio = space_hop_ratios(c);
   a.m4 = (float)(4.0 + c->M);
@@ -834,10 +1082,18 @@ int sap_apply_fused(dp_ctx* c, SapState& s, const Blocking& b, int ncy, int nmr)
     for (int colour = 0; colour < 2; ++colour) {
       a.colour = colour;
       a.own_zero = cy == 0;
-      if (cy == 0 && colour == 0)
-        hipLaunchKernelGGL(sap_block_kernel<true>, dim3(b.nhalf), dim3(kSapThreads), 0, c->stream, a);
-      else
-        hipLaunchKernelGGL(sap_block_kernel<false>, dim3(b.nhalf), dim3(kSapThreads), 0, c->stream, a);
+      const bool first = cy == 0 && colour == 0;
+      if (b.vol <= kSapThreads) {
+        if (first)
+          hipLaunchKernelGGL(sap_block_kernel<true>, dim3(b.nhalf), dim3(kSapThreads), 0, c->stream, a);
+        else
+          hipLaunchKernelGGL(sap_block_kernel<false>, dim3(b.nhalf), dim3(kSapThreads), 0, c->stream, a);
+      } else {
+        if (first)
+          hipLaunchKernelGGL(sap_block_big_kernel<true>, dim3(b.nhalf), dim3(kSapBigThreads), 0, c->stream, a);
+        else
+          hipLaunchKernelGGL(sap_block_big_kernel<false>, dim3(b.nhalf), dim3(kSapBigThreads), 0, c->stream, a);
+      }
       DP_HIP(c, hipGetLastError());
     }
   return DP_OK;
@@ -975,25 +1231,34 @@ extern "C" int dp_solve_sap(dp_ctx* c, const double* eta, const dp_sap_params* p
       DP_TRY(precondition(c, s, b, p->ncy, p->nmr, s.r, s.z[k]));
       DP_TRY(apply_full(c, s, F64, s.z[k], s.w[k]));
       ++iters;
+      // modified Gram-Schmidt against the earlier w_j, normalisation,
+      // gamma_k = <w_k, r> and r -= gamma_k w_k, with every coefficient
+      // formed and used on the device; one copy to the host per iteration
+      double* gd = s.gcr.as<double>();
       for (int j = 0; j < k; ++j) {
-        zc cj;
-        DP_TRY(vec_dot(c, s, s.w[j], s.w[k], &cj));
-        cc[(size_t)j * nkv + k] = cj;
-        DP_TRY(vec_update(c, 0, -cj, s.w[j], s.w[k]));
+        double* cj = gd + gcr_cc(nkv, j, k);
+        DP_TRY(vec_dot_dev(c, s, s.w[j], s.w[k], 0, nullptr, cj));
+        DP_TRY(vec_update_dev(c, 0, cj, -1.0, s.w[j], s.w[k]));
       }
-      zc b2;
-      DP_TRY(vec_dot(c, s, s.w[k], s.w[k], &b2));
-      bn[k] = std::sqrt(b2.real());
+      double* bk = gd + gcr_bn(nkv, k);
+      DP_TRY(vec_dot_dev(c, s, s.w[k], s.w[k], 1, nullptr, bk));
+      DP_TRY(vec_update_dev(c, 1, bk, 1.0, s.w[k], s.w[k]));
+      double* gk = gd + gcr_gam(nkv, k);
+      DP_TRY(vec_dot_dev(c, s, s.w[k], s.r, 2, bk, gk));
+      DP_TRY(vec_update_dev(c, 0, gk, -1.0, s.w[k], s.r));
+      DP_TRY(vec_dot_dev(c, s, s.r, s.r, 0, nullptr, gd + gcr_rn(nkv)));
+      DP_HIP(c, hipMemcpyAsync(s.h_gcr.data(), gd, sizeof(double) * gcr_len(nkv), hipMemcpyDeviceToHost, c->stream));
+      DP_HIP(c, hipStreamSynchronize(c->stream));
+      const double* hg = s.h_gcr.data();
+      for (int j = 0; j < k; ++j)
+        cc[(size_t)j * nkv + k] = zc(hg[gcr_cc(nkv, j, k)], hg[gcr_cc(nkv, j, k) + 1]);
+      bn[k] = hg[gcr_bn(nkv, k)];
       if (!(bn[k] > 0) || !std::isfinite(bn[k])) {
         breakdown = true;
         break;
       }
-      DP_TRY(vec_update(c, 1, zc(1.0 / bn[k], 0.0), s.w[k], s.w[k]));
-      DP_TRY(vec_dot(c, s, s.w[k], s.r, &gam[k]));
-      DP_TRY(vec_update(c, 0, -gam[k], s.w[k], s.r));
-      zc r2;
-      DP_TRY(vec_dot(c, s, s.r, s.r, &r2));
-      rn = std::sqrt(r2.real());
+      gam[k] = zc(hg[gcr_gam(nkv, k)], hg[gcr_gam(nkv, k) + 1]);
+      rn = std::sqrt(hg[gcr_rn(nkv)]);
       if (rn <= target) {
         ++k;
         break;

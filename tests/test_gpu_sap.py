@@ -54,16 +54,21 @@ def test_sap_rejects_bad_blocks():
 
 
 # One application of the preconditioner against the oracle's, element by
-# element.  Blocks of at most 256 sites run the fused kernel (one launch per
-# colour pass) with FP32 block solves; DP_SAP_FUSED=0 keeps the
-# launch-per-step path; FP64 block solves always take the latter.  The FP32
+# element.  With FP32 block solves, blocks of at most 256 sites run the fused
+# kernel (one launch per colour pass), blocks of up to 1536 sites its
+# large-block variant; DP_SAP_FUSED=0, larger blocks and FP64 block solves
+# take the launch-per-step path.  The FP32
 # bound: each of the 5 x 2 passes rounds every residual and correction to
 # FP32 (2^-24 relative) through 4 minimal-residual steps with O(10)-term
 # sums, which stays within a few 1e-6 of the FP64 result in norm.
 @pytest.mark.parametrize("dims,block", [((8, 4, 8, 4), (4, 2, 4, 2)),   # 64-site blocks, 16 of them
                                         ((8, 8, 8, 8), (4, 4, 4, 4)),   # 256 sites: every lane of the workgroup
                                         ((4, 4, 4, 8), (2, 2, 2, 2)),   # 16 sites: most lanes idle
-                                        ((8, 6, 4, 4), (4, 3, 2, 2))])  # odd extent within a block
+                                        ((8, 6, 4, 4), (4, 3, 2, 2)),   # odd extent within a block
+                                        ((16, 8, 8, 8), (8, 4, 4, 4)),  # 512 sites: the large-block kernel
+                                        ((12, 12, 12, 12), (6, 6, 6, 6)),  # 1296 sites (the 48x24^3 blocking)
+                                        ((16, 12, 8, 16), (8, 6, 4, 8)),   # 1536 sites: its largest block
+                                        ((16, 16, 16, 8), (8, 8, 8, 4))])  # 2048 sites: launch per step
 @pytest.mark.parametrize("path", ["fused", "steps", "f64"])
 def test_sap_precondition_vs_oracle(dims, block, path, monkeypatch):
     log(f"test_sap_precondition_vs_oracle {dims} {block} {path}")
