@@ -851,6 +851,76 @@ __global__ void __launch_bounds__(64) dot_finish_kernel(const double* __restrict
   out[1] = im;
 }
 
+// One Gram-Schmidt step of GCR in one pass: the update of y as in
+// vec_update_dev_kernel (op, coef, sgn, x), then the block partials of a dot
+// product involving the updated y, as vec_dot_kernel forms them (same grid,
+// same order, same arithmetic): dmode 0: <z, y>, 1: <y, z>, 2: <y, y>.
+__global__ void __launch_bounds__(kBlock) vec_update_dot_kernel(Geom g, int op, const double* __restrict__ coef,
+                                                                double sgn, SpinorRef x, SpinorRef y, int dmode,
+                                                                SpinorRef z, double* __restrict__ partials) {
+  __shared__ double lds[2][kBlock / 64];
+  const double c0 = coef[0], c1 = coef[1];
+  const bool skip = op == 1 && !(c0 > 0.0 && isfinite(c0));
+  double re = 0.0, im = 0.0;
+  const long n = 2L * g.Vh;
+  for (long s = (long)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (long)gridDim.x * blockDim.x) {
+    const int p = (int)(s / g.Vh), i = (int)(s - (long)p * g.Vh);
+    cx<double> vx[12], vy[12];
+    SpinorIO<F64>::load(y, p, i, g.Vp, vy);
+    if (!skip) {
+      if (op == 0) {
+        SpinorIO<F64>::load(x, p, i, g.Vp, vx);
+        const cx<double> a{sgn * c0, sgn * c1};
+#pragma unroll
+        for (int c = 0; c < 12; ++c) vy[c] = vy[c] + cmul(a, vx[c]);
+      } else {
+        const double ar = 1.0 / c0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) vy[c] = ar * vy[c];
+      }
+      SpinorIO<F64>::store(y, p, i, g.Vp, vy);
+    }
+    if (dmode == 2) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        re += vy[c].x * vy[c].x + vy[c].y * vy[c].y;
+        im += vy[c].x * vy[c].y - vy[c].y * vy[c].x;
+      }
+    } else {
+      SpinorIO<F64>::load(z, p, i, g.Vp, vx);
+      if (dmode == 0) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          re += vx[c].x * vy[c].x + vx[c].y * vy[c].y;
+          im += vx[c].x * vy[c].y - vx[c].y * vy[c].x;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          re += vy[c].x * vx[c].x + vy[c].y * vx[c].y;
+          im += vy[c].x * vx[c].y - vy[c].y * vx[c].x;
+        }
+      }
+    }
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if ((threadIdx.x & 63) == 0) {
+    lds[0][threadIdx.x >> 6] = re;
+    lds[1][threadIdx.x >> 6] = im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) {
+      a += lds[0][q];
+      b += lds[1][q];
+    }
+    partials[2 * blockIdx.x] = a;
+    partials[2 * blockIdx.x + 1] = b;
+  }
+}
+
 // vec_update_kernel with its coefficient on the device: op 0: y += sgn coef x
 // (coef complex); op 1: y = y / coef[0] (a norm; y is left alone when it is
 // zero or not finite)
@@ -996,6 +1066,18 @@ int vec_dot_dev(dp_ctx* c, SapState& s, const Field& x, const Field& y, int mode
                      s.partials.as<double>());
   DP_HIP(c, hipGetLastError());
   hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(64), 0, c->stream, s.partials.as<double>(), mode, guard, out);
+  DP_HIP(c, hipGetLastError());
+  return DP_OK;
+}
+
+// y updated as by vec_update_dev, then out = the finished dot product of
+// vec_update_dot_kernel's dmode (finished in dot_finish_kernel's fmode)
+int vec_update_dot_dev(dp_ctx* c, SapState& s, int op, const double* coef, double sgn, const Field& x,
+                       const Field& y, int dmode, const Field& z, int fmode, const double* guard, double* out) {
+  hipLaunchKernelGGL(vec_update_dot_kernel, dim3(kDotBlocks), dim3(kBlock), 0, c->stream, c->g, op, coef, sgn,
+                     x.ref(), y.ref(), dmode, z.ref(), s.partials.as<double>());
+  DP_HIP(c, hipGetLastError());
+  hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(64), 0, c->stream, s.partials.as<double>(), fmode, guard, out);
   DP_HIP(c, hipGetLastError());
   return DP_OK;
 }
@@ -1233,20 +1315,24 @@ extern "C" int dp_solve_sap(dp_ctx* c, const double* eta, const dp_sap_params* p
       ++iters;
       // modified Gram-Schmidt against the earlier w_j, normalisation,
       // gamma_k = <w_k, r> and r -= gamma_k w_k, with every coefficient
-      // formed and used on the device; one copy to the host per iteration
+      // formed and used on the device (each update shares its pass with the
+      // next dot product); one copy to the host per iteration
       double* gd = s.gcr.as<double>();
-      for (int j = 0; j < k; ++j) {
-        double* cj = gd + gcr_cc(nkv, j, k);
-        DP_TRY(vec_dot_dev(c, s, s.w[j], s.w[k], 0, nullptr, cj));
-        DP_TRY(vec_update_dev(c, 0, cj, -1.0, s.w[j], s.w[k]));
-      }
       double* bk = gd + gcr_bn(nkv, k);
-      DP_TRY(vec_dot_dev(c, s, s.w[k], s.w[k], 1, nullptr, bk));
-      DP_TRY(vec_update_dev(c, 1, bk, 1.0, s.w[k], s.w[k]));
       double* gk = gd + gcr_gam(nkv, k);
-      DP_TRY(vec_dot_dev(c, s, s.w[k], s.r, 2, bk, gk));
-      DP_TRY(vec_update_dev(c, 0, gk, -1.0, s.w[k], s.r));
-      DP_TRY(vec_dot_dev(c, s, s.r, s.r, 0, nullptr, gd + gcr_rn(nkv)));
+      if (k == 0) {
+        DP_TRY(vec_dot_dev(c, s, s.w[k], s.w[k], 1, nullptr, bk));
+      } else {
+        DP_TRY(vec_dot_dev(c, s, s.w[0], s.w[k], 0, nullptr, gd + gcr_cc(nkv, 0, k)));
+        for (int j = 1; j < k; ++j)  // w_k -= c_{j-1,k} w_{j-1}, then c_jk = <w_j, w_k>
+          DP_TRY(vec_update_dot_dev(c, s, 0, gd + gcr_cc(nkv, j - 1, k), -1.0, s.w[j - 1], s.w[k], 0, s.w[j], 0,
+                                    nullptr, gd + gcr_cc(nkv, j, k)));
+        DP_TRY(vec_update_dot_dev(c, s, 0, gd + gcr_cc(nkv, k - 1, k), -1.0, s.w[k - 1], s.w[k], 2, s.w[k], 1,
+                                  nullptr, bk));
+      }
+      // w_k /= b_k, then gamma_k = <w_k, r>; r -= gamma_k w_k, then |r|^2
+      DP_TRY(vec_update_dot_dev(c, s, 1, bk, 1.0, s.w[k], s.w[k], 1, s.r, 2, bk, gk));
+      DP_TRY(vec_update_dot_dev(c, s, 0, gk, -1.0, s.w[k], s.r, 2, s.r, 0, nullptr, gd + gcr_rn(nkv)));
       DP_HIP(c, hipMemcpyAsync(s.h_gcr.data(), gd, sizeof(double) * gcr_len(nkv), hipMemcpyDeviceToHost, c->stream));
       DP_HIP(c, hipStreamSynchronize(c->stream));
       const double* hg = s.h_gcr.data();
