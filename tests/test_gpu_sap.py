@@ -113,3 +113,53 @@ def test_sap_fused_matches_steps(monkeypatch):
     err = np.linalg.norm(out["1"] - out["0"]) / np.linalg.norm(out["0"])
     log(f"  fused vs steps {err:.2e}")
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("dims,block", [((8, 8, 8, 8), (4, 4, 4, 4)), ((12, 12, 12, 12), (6, 6, 6, 6))])
+def test_sap_precondition_dirichlet_time(dims, block):
+    """Dirichlet time boundary (bc_t = 0, the Schroedinger-functional hops):
+    the hops across x0 = T-1 -> 0 drop in the block residual of both fused
+    kernels, as in the oracle."""
+    log(f"test_sap_precondition_dirichlet_time {dims} {block}")
+    U = synth.gauge_su3(dims, 0.4, 49)
+    C = oracle.clover(U, 1.6)
+    M = 0.2
+    r = synth.random_spinor(dims, 50)
+    want = oracle.sap_apply(U, C, M, r, block, bc_t=0)
+    with lattice(dims, bc_t=0) as L:
+        L.set_gauge(U)
+        L.set_clover(1.6)
+        L.set_mass(M)
+        got = L.sap_precondition(r, block)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    worst = np.abs(got - want).max() / np.abs(want).max()
+    log(f"  relative error {err:.2e}, max {worst:.2e}")
+    assert err < 1e-5 and worst < 1e-5
+
+
+def test_sap_precondition_full_size_32c64():
+    """The preconditioner at the SAP study's full size and launch shape
+    (64x32^3, 4^4 blocks, cosh factorisation alpha0 = 0.4, M = 0.05) against
+    the oracle's, element by element over all 2.1 M sites."""
+    cfg = synth.config("su3_32c64")
+    dims = cfg["dims"]
+    block = (4, 4, 4, 4)
+    log("test_sap_precondition_full_size_32c64: fields")
+    U = synth.gauge_su3(dims, cfg["eps"], cfg["seed"])
+    C = oracle.clover(U, cfg["csw"])
+    beta = synth.beta_cosh_paper(dims, 0.4)
+    r = synth.random_spinor(dims, 51)
+    log("  oracle")
+    want = oracle.sap_apply(U, C, 0.05, r, block, beta=beta)
+    del C
+    log("  GPU")
+    with lattice(dims) as L:
+        L.set_gauge(U)
+        L.set_clover(cfg["csw"])
+        L.set_mass(0.05)
+        L.set_beta(beta)
+        got = L.sap_precondition(r, block)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    worst = np.abs(got - want).max() / np.abs(want).max()
+    log(f"  relative error {err:.2e}, max {worst:.2e}")
+    assert err < 1e-5 and worst < 1e-5
