@@ -851,10 +851,12 @@ __global__ void __launch_bounds__(64) dot_finish_kernel(const double* __restrict
   out[1] = im;
 }
 
-// One Gram-Schmidt step of GCR in one pass: the update of y as in
-// vec_update_dev_kernel (op, coef, sgn, x), then the block partials of a dot
-// product involving the updated y, as vec_dot_kernel forms them (same grid,
-// same order, same arithmetic): dmode 0: <z, y>, 1: <y, z>, 2: <y, y>.
+// One Gram-Schmidt step of GCR in one pass: the update of y with its
+// coefficient on the device (op 0: y += sgn coef x, coef complex; op 1:
+// y = y / coef[0], a norm, y left alone when it is zero or not finite), then
+// the block partials of a dot product involving the updated y, as
+// vec_dot_kernel forms them (same grid, order and arithmetic): dmode 0:
+// <z, y>, 1: <y, z>, 2: <y, y>.
 __global__ void __launch_bounds__(kBlock) vec_update_dot_kernel(Geom g, int op, const double* __restrict__ coef,
                                                                 double sgn, SpinorRef x, SpinorRef y, int dmode,
                                                                 SpinorRef z, double* __restrict__ partials) {
@@ -921,30 +923,6 @@ __global__ void __launch_bounds__(kBlock) vec_update_dot_kernel(Geom g, int op, 
   }
 }
 
-// vec_update_kernel with its coefficient on the device: op 0: y += sgn coef x
-// (coef complex); op 1: y = y / coef[0] (a norm; y is left alone when it is
-// zero or not finite)
-__global__ void __launch_bounds__(kBlock) vec_update_dev_kernel(Geom g, int op, const double* __restrict__ coef,
-                                                                double sgn, SpinorRef x, SpinorRef y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = blockIdx.y;
-  if (i >= g.Vh) return;
-  const double c0 = coef[0], c1 = coef[1];
-  if (op == 1 && !(c0 > 0.0 && isfinite(c0))) return;
-  cx<double> vx[12], vy[12];
-  SpinorIO<F64>::load(y, p, i, g.Vp, vy);
-  if (op == 0) {
-    SpinorIO<F64>::load(x, p, i, g.Vp, vx);
-    const cx<double> a{sgn * c0, sgn * c1};
-#pragma unroll
-    for (int c = 0; c < 12; ++c) vy[c] = vy[c] + cmul(a, vx[c]);
-  } else {
-    const double ar = 1.0 / c0;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) vy[c] = ar * vy[c];
-  }
-  SpinorIO<F64>::store(y, p, i, g.Vp, vy);
-}
 
 }  // namespace
 
@@ -1070,8 +1048,8 @@ int vec_dot_dev(dp_ctx* c, SapState& s, const Field& x, const Field& y, int mode
   return DP_OK;
 }
 
-// y updated as by vec_update_dev, then out = the finished dot product of
-// vec_update_dot_kernel's dmode (finished in dot_finish_kernel's fmode)
+// y updated by vec_update_dot_kernel's op, then out = the dot product of its
+// dmode (finished in dot_finish_kernel's fmode)
 int vec_update_dot_dev(dp_ctx* c, SapState& s, int op, const double* coef, double sgn, const Field& x,
                        const Field& y, int dmode, const Field& z, int fmode, const double* guard, double* out) {
   hipLaunchKernelGGL(vec_update_dot_kernel, dim3(kDotBlocks), dim3(kBlock), 0, c->stream, c->g, op, coef, sgn,
@@ -1082,12 +1060,6 @@ int vec_update_dot_dev(dp_ctx* c, SapState& s, int op, const double* coef, doubl
   return DP_OK;
 }
 
-int vec_update_dev(dp_ctx* c, int op, const double* coef, double sgn, const Field& x, const Field& y) {
-  hipLaunchKernelGGL(vec_update_dev_kernel, site_grid(c->g), dim3(kBlock), 0, c->stream, c->g, op, coef, sgn,
-                     x.ref(), y.ref());
-  DP_HIP(c, hipGetLastError());
-  return DP_OK;
-}
 
 template <int PI, int PO>
 int convert(dp_ctx* c, const Field& x, const Field& y) {
