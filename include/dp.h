@@ -262,6 +262,13 @@ typedef struct {
 } dp_sap_params;
 /* One right-hand side (host layout); S and cpp (T doubles) nullable. */
 int dp_solve_sap(dp_ctx* ctx, const double* eta, const dp_sap_params* p, double* S, double* cpp, dp_info* info);
+/* Paper: as dp_solve_sap (Table 1 and the solver it cites).
+ * Same with eta and S in device memory (host layout, V x 12 complex doubles;
+ * S nullable; they must not overlap, else DP_ERR_INVALID_ARG); cpp and info
+ * on the host.  The library first waits for hip_stream (nullable), then works
+ * on its own stream and returns when S and cpp are complete. */
+int dp_solve_sap_dev(dp_ctx* ctx, const void* eta_dev, const dp_sap_params* p, void* S_dev, double* cpp,
+                     dp_info* info, void* hip_stream);
 
 /* Paper: the Schwarz preconditioner of the solver of Table 1 (the procedure
  * it cites), on the preconditioned operator D' of eqs. redefa, betaa.

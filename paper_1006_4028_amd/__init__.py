@@ -269,6 +269,23 @@ class Lattice:
         self._check(rc, allow=(L.DP_ERR_NOT_CONVERGED,) if allow_unconverged else ())
         return S, cpp, self._infos([info])[0]
 
+    def solve_sap_dev(self, eta_t, S_t=None, block=(4, 4, 4, 4), r=1e-10, ncy=5, nmr=4, nkv=16, precision="f32",
+                      max_iter=1000, allow_unconverged=False):
+        """SAP+GCR with eta_t (and S_t) torch CUDA tensors in host layout;
+        returns (cpp, info)."""
+        import torch
+        assert eta_t.is_cuda and eta_t.is_contiguous() and eta_t.numel() * eta_t.element_size() == self.V * 12 * 16
+        cpp = np.zeros(self.T)
+        info = L.dp_info()
+        p = L.dp_sap_params(float(r), (ctypes.c_int * 4)(*[int(b) for b in block]), int(ncy), int(nmr), int(nkv),
+                            L.DP_PREC[precision], int(max_iter))
+        stream = torch.cuda.current_stream(eta_t.device).cuda_stream
+        rc = self._L.dp_solve_sap_dev(self._h, ctypes.c_void_p(eta_t.data_ptr()), ctypes.byref(p),
+                                      ctypes.c_void_p(S_t.data_ptr()) if S_t is not None else None, _ptr(cpp),
+                                      ctypes.byref(info), ctypes.c_void_p(stream))
+        self._check(rc, allow=(L.DP_ERR_NOT_CONVERGED,) if allow_unconverged else ())
+        return cpp, self._infos([info])[0]
+
     def sap_precondition(self, r, block, ncy=5, nmr=4, precision="f32"):
         """One application psi = M r of the SAP preconditioner (host layout,
         preconditioned variables)."""

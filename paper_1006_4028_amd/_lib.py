@@ -33,7 +33,7 @@ EXPORTED = [
     "dp_sf_wall_sources", "dp_set_clover",
     "dp_set_clover_field", "dp_set_mass", "dp_set_kappa", "dp_set_alpha", "dp_set_alpha_space", "dp_apply",
     "dp_apply_dev", "dp_apply_dev_slots", "dp_apply_dev_noalloc", "dp_point_sources", "dp_solve", "dp_solve_sap",
-    "dp_sap_precondition", "dp_solve_dev", "dp_footprint_bytes", "dp_set_timing", "dp_get_timing", "dp_get_timing_samples",
+    "dp_solve_sap_dev", "dp_sap_precondition", "dp_solve_dev", "dp_footprint_bytes", "dp_set_timing", "dp_get_timing", "dp_get_timing_samples",
     "dp_batch_open", "dp_batch_close",
     "dp_batch_admit", "dp_batch_step", "dp_batch_harvest", "dp_batch_status", "dp_batch_device_bytes",
 ]
@@ -108,6 +108,7 @@ def lib():
     L.dp_set_alpha_space.argtypes = [vp, dp, dp, dp]
     L.dp_solve_sap.argtypes = [vp, dp, ctypes.POINTER(dp_sap_params), dp, dp, ctypes.POINTER(dp_info)]
     L.dp_sap_precondition.argtypes = [vp, dp, ctypes.POINTER(dp_sap_params), dp]
+    L.dp_solve_sap_dev.argtypes = [vp, vp, ctypes.POINTER(dp_sap_params), vp, dp, ctypes.POINTER(dp_info), vp]
     L.dp_apply.argtypes = [vp, dp, dp, ctypes.c_int]
     L.dp_apply_dev.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
     L.dp_apply_dev_slots.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, dp, dp, vp]

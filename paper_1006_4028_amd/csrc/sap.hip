@@ -1247,23 +1247,21 @@ extern "C" int dp_sap_precondition(dp_ctx* c, const double* r, const dp_sap_para
   return DP_OK;
 }
 
-extern "C" int dp_solve_sap(dp_ctx* c, const double* eta, const dp_sap_params* p, double* S, double* cpp,
-                            dp_info* info) {
-  if (!c || !eta || !p) return DP_ERR_INVALID_ARG;
+namespace dp {
+namespace {
+
+// The SAP+GCR solve (after sap_prepare) from a source in device memory (host
+// layout); the solution goes to S_dev (device, host layout) if not null, then
+// to S_host; t0 is the start of the timed solve.
+int sap_solve(dp_ctx* c, const Blocking& b, const double2* eta_dev, const dp_sap_params* p, double2* S_dev,
+              double* S_host, double* cpp, dp_info* info, double t0) {
   const Geom& g = c->g;
-  if (!(p->r > 0) || !std::isfinite(p->r) || p->nkv < 1 || p->nkv > 64 || p->max_iter < 1)
-    return fail(c, DP_ERR_INVALID_ARG, "bad residue, ncy, nmr, nkv (1..64) or max_iter");
-  Blocking b;
-  DP_TRY(sap_prepare(c, p, p->nkv, &b));
   SapState& s = *c->sap;
-  const double t0 = now_s();
-  // eta' = beta eta
   const size_t bytes = (size_t)2 * g.Vh * 12 * sizeof(double2);
-  DP_HIP(c, c->scratch_aos.reserve(bytes));
-  DP_HIP(c, hipMemcpyAsync(c->scratch_aos.p, eta, bytes, hipMemcpyHostToDevice, c->stream));
+  // eta' = beta eta
   for (int par = 0; par < 2; ++par)
-    DP_HIP(c, launch_spinor_import(g, c->scratch_aos.as<double2>(), 1, 0, par, s.eta.ref(par), s.alpha.as<double>(),
-                                   space_profile(c), c->stream));
+    DP_HIP(c, launch_spinor_import(g, eta_dev, 1, 0, par, s.eta.ref(par), s.alpha.as<double>(), space_profile(c),
+                                   c->stream));
   zc e2;
   DP_TRY(vec_dot(c, s, s.eta, s.eta, &e2));
   const double target = p->r * std::sqrt(e2.real());
@@ -1343,9 +1341,11 @@ extern "C" int dp_solve_sap(dp_ctx* c, const double* eta, const dp_sap_params* p
     else if (rn <= target) status = DP_OK;
   }
   // S = x / beta, C_PP
-  DP_HIP(c, launch_spinor_export(g, s.x.ref(0), s.x.ref(1), 1, s.alpha.as<double>(), space_profile(c),
-                                 c->scratch_aos.as<double2>(), 0, c->stream));
-  if (S) DP_HIP(c, hipMemcpyAsync(S, c->scratch_aos.p, bytes, hipMemcpyDeviceToHost, c->stream));
+  if (S_dev) {
+    DP_HIP(c, launch_spinor_export(g, s.x.ref(0), s.x.ref(1), 1, s.alpha.as<double>(), space_profile(c), S_dev, 0,
+                                   c->stream));
+    if (S_host) DP_HIP(c, hipMemcpyAsync(S_host, S_dev, bytes, hipMemcpyDeviceToHost, c->stream));
+  }
   if (cpp) {
     DP_HIP(c, s.cpp.reserve(sizeof(double) * g.T));
     DP_HIP(c, launch_cpp(g, s.x.ref(0), s.x.ref(1), 1, s.alpha.as<double>(), space_profile(c), nullptr,
@@ -1369,4 +1369,46 @@ extern "C" int dp_solve_sap(dp_ctx* c, const double* eta, const dp_sap_params* p
   if (status == DP_ERR_BREAKDOWN) return fail(c, status, "GCR broke down (zero preconditioned direction)");
   if (status == DP_ERR_NONFINITE) return fail(c, status, "a residual became NaN or Inf");
   return DP_OK;
+}
+
+int sap_check(dp_ctx* c, const dp_sap_params* p) {
+  if (!(p->r > 0) || !std::isfinite(p->r) || p->nkv < 1 || p->nkv > 64 || p->max_iter < 1)
+    return fail(c, DP_ERR_INVALID_ARG, "bad residue, ncy, nmr, nkv (1..64) or max_iter");
+  return DP_OK;
+}
+
+}  // namespace
+}  // namespace dp
+
+extern "C" int dp_solve_sap(dp_ctx* c, const double* eta, const dp_sap_params* p, double* S, double* cpp,
+                            dp_info* info) {
+  if (!c || !eta || !p) return DP_ERR_INVALID_ARG;
+  DP_TRY(sap_check(c, p));
+  Blocking b;
+  DP_TRY(sap_prepare(c, p, p->nkv, &b));
+  const double t0 = now_s();
+  // the source through the context's staging buffer, which takes the
+  // solution afterwards
+  const size_t bytes = (size_t)2 * c->g.Vh * 12 * sizeof(double2);
+  DP_HIP(c, c->scratch_aos.reserve(bytes));
+  DP_HIP(c, hipMemcpyAsync(c->scratch_aos.p, eta, bytes, hipMemcpyHostToDevice, c->stream));
+  double2* st = c->scratch_aos.as<double2>();
+  return sap_solve(c, b, st, p, S ? st : nullptr, S, cpp, info, t0);
+}
+
+extern "C" int dp_solve_sap_dev(dp_ctx* c, const void* eta_dev, const dp_sap_params* p, void* S_dev, double* cpp,
+                                dp_info* info, void* hip_stream) {
+  if (!c || !eta_dev || !p) return DP_ERR_INVALID_ARG;
+  DP_TRY(sap_check(c, p));
+  const size_t bytes = (size_t)2 * c->g.Vh * 12 * sizeof(double2);
+  const char* e0 = static_cast<const char*>(eta_dev);
+  const char* s0 = static_cast<const char*>(S_dev);
+  if (S_dev && e0 < s0 + bytes && s0 < e0 + bytes) return fail(c, DP_ERR_INVALID_ARG, "eta and S overlap");
+  DP_HIP(c, hipSetDevice(c->device));
+  if (hip_stream) DP_HIP(c, hipStreamSynchronize((hipStream_t)hip_stream));
+  Blocking b;
+  DP_TRY(sap_prepare(c, p, p->nkv, &b));
+  const double t0 = now_s();
+  return sap_solve(c, b, static_cast<const double2*>(eta_dev), p, static_cast<double2*>(S_dev), nullptr, cpp, info,
+                   t0);
 }

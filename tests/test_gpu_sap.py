@@ -163,3 +163,30 @@ def test_sap_precondition_full_size_32c64():
     worst = np.abs(got - want).max() / np.abs(want).max()
     log(f"  relative error {err:.2e}, max {worst:.2e}")
     assert err < 1e-5 and worst < 1e-5
+
+
+def test_solve_sap_dev_matches_host():
+    """The device-buffer SAP+GCR entry point gives bitwise the host variant's
+    solution and C_PP (same kernels, same order); overlapping eta and S are
+    rejected."""
+    import torch
+    import paper_1006_4028_amd as dp
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    log("test_solve_sap_dev_matches_host")
+    U = synth.gauge_su3(dims, 0.4, 52)
+    eta = synth.point_sources_12(dims, (1, 0, 0, 0))[5]
+    with lattice(dims) as L:
+        L.set_gauge(U)
+        L.set_clover(1.6)
+        L.set_mass(0.05)
+        L.set_beta(synth.beta_cosh_paper(dims, 0.3))
+        S, cpp, info = L.solve_sap(eta, block, r=1e-10, nkv=8)
+        e_t = torch.from_numpy(np.ascontiguousarray(eta)).cuda()
+        S_t = torch.zeros_like(e_t)
+        cpp_d, info_d = L.solve_sap_dev(e_t, S_t, block, r=1e-10, nkv=8)
+        assert info_d["iters"] == info["iters"]
+        np.testing.assert_array_equal(S_t.cpu().numpy(), S)
+        np.testing.assert_array_equal(cpp_d, cpp)
+        with pytest.raises(dp.DPError) as e:
+            L.solve_sap_dev(e_t, e_t, block, r=1e-10, nkv=8)
+        assert e.value.code == -1
