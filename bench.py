@@ -397,7 +397,10 @@ def sap_study(only=None):
     four-direction cosh factorisation (eq. betaa) for alpha0 in {0, 0.2, 0.4};
     48 x 24^3 with 6^4 blocks at r = 1e-11 (the D5 shape) and 64 x 32^3 with
     4^4 blocks at r = 1e-10 (the E shape); M in {0.01, 0.05}; FP32 block
-    solves, ncy = 5, nmr = 4, nkv = 16; one point-source column."""
+    solves, ncy = 5, nmr = 4, nkv = 16; one point-source column, source and
+    solution resident on the device (the seconds exclude host transfers)."""
+    import numpy as np
+    import torch
     import paper_1006_4028_amd as dp
     import synth
     out = []
@@ -412,11 +415,13 @@ def sap_study(only=None):
         del U
         L.set_clover(cfg["csw"])
         eta = synth.point_sources_12(dims, (0, 0, 0, 0))[0]
+        eta_t = torch.from_numpy(np.ascontiguousarray(eta)).cuda()
+        S_t = torch.zeros_like(eta_t)
         for M in (0.01, 0.05):
             L.set_mass(M)
             for a0 in (0.0, 0.2, 0.4):
                 L.set_beta(synth.beta_cosh_paper(dims, a0))
-                _, _, info = L.solve_sap(eta, block, r=r, max_iter=2000)
+                _, info = L.solve_sap_dev(eta_t, S_t, block, r=r, max_iter=2000)
                 rec = {"workload": name, "block": block, "r": r, "M": M, "alpha0": a0, "iters": info["iters"],
                        "restarts": info["outer"], "seconds": round(info["seconds"], 3),
                        "true_res": info["true_res"], "status": info["status"]}
