@@ -203,7 +203,7 @@ def main():
     if args.pmc_summary:
         return pmc_summary(*args.pmc_summary)
     if args.sap_study:
-        return sap_study(args.sap_workload)
+        return sap_study(args.sap_workload, not args.no_cpu_baseline)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (one process drives one GPU)",
               file=sys.stderr)
@@ -391,19 +391,23 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def sap_study(only=None):
+def sap_study(only=None, cpu_baseline=True):
     """The analogue of the paper's Table 1 on the synthetic fields: SAP+GCR
     iterations (and seconds) to invert the light-quark Dirac equation with the
     four-direction cosh factorisation (eq. betaa) for alpha0 in {0, 0.2, 0.4};
     48 x 24^3 with 6^4 blocks at r = 1e-11 (the D5 shape) and 64 x 32^3 with
     4^4 blocks at r = 1e-10 (the E shape); M in {0.01, 0.05}; FP32 block
     solves, ncy = 5, nmr = 4, nkv = 16; one point-source column, source and
-    solution resident on the device (the seconds exclude host transfers)."""
+    solution resident on the device (the seconds exclude host transfers).
+    The CPU baseline leg times one application of the oracle's SAP
+    preconditioner (M = 0.05, alpha0 = 0.4) on each lattice, against the
+    GPU's time per GCR iteration (one application, the FP64 operator and the
+    Gram-Schmidt step)."""
     import numpy as np
     import torch
     import paper_1006_4028_amd as dp
     import synth
-    out = []
+    out, cpu = [], []
     for name, block, r in (("su3_24c48", (6, 6, 6, 6), 1e-11), ("su3_32c64", (4, 4, 4, 4), 1e-10)):
         if only and name != only:
             continue
@@ -428,7 +432,23 @@ def sap_study(only=None):
                 log(json.dumps(rec))
                 out.append(rec)
         L.close()
-    print(json.dumps({"sap_study": out}), flush=True)
+        del eta_t, S_t
+        if cpu_baseline:
+            import oracle
+            U = synth.gauge_su3(dims, cfg["eps"], cfg["seed"])
+            C = oracle.clover(U, cfg["csw"])
+            r_h = synth.random_spinor(dims, 51)
+            log(f"CPU oracle: one SAP application on {name}")
+            t0 = time.perf_counter()
+            oracle.sap_apply(U, C, 0.05, r_h, block, beta=synth.beta_cosh_paper(dims, 0.4))
+            t_or = time.perf_counter() - t0
+            del U, C, r_h
+            per_it = min(x["seconds"] / x["iters"] for x in out if x["workload"] == name)
+            rec = {"workload": name, "kind": "oracle", "cores": oracle.get_threads(),
+                   "oracle_sap_apply_s": round(t_or, 2), "gpu_ms_per_gcr_iteration": round(1e3 * per_it, 2)}
+            log(json.dumps(rec))
+            cpu.append(rec)
+    print(json.dumps({"sap_study": out, "cpu_baseline": cpu}), flush=True)
 
 
 MALL_BYTES = 256 * 2 ** 20
