@@ -190,3 +190,31 @@ def test_solve_sap_dev_matches_host():
         with pytest.raises(dp.DPError) as e:
             L.solve_sap_dev(e_t, e_t, block, r=1e-10, nkv=8)
         assert e.value.code == -1
+
+
+def test_sap_nonfinite_reports_and_recovers():
+    """A time profile whose hop ratio (1e40) exceeds the FP32 range makes the
+    FP32 block solves non-finite: GCR's device-side guards keep the norm and
+    coefficient steps from acting on it, the solve ends with
+    DP_ERR_NONFINITE, and the context solves normally afterwards."""
+    import paper_1006_4028_amd as dp
+    dims, block = (8, 4, 8, 4), (4, 2, 4, 2)
+    log("test_sap_nonfinite_reports_and_recovers")
+    U = synth.gauge_su3(dims, 0.4, 53)
+    C = oracle.clover(U, 1.6)
+    eta = synth.point_sources_12(dims, (0, 0, 0, 0))[0]
+    alpha = np.ones(dims[0])
+    alpha[-1] = 1e-40
+    with lattice(dims, bc_t=0) as L:
+        L.set_gauge(U)
+        L.set_clover(1.6)
+        L.set_mass(0.2)
+        L.set_alpha(alpha)
+        with pytest.raises(dp.DPError) as e:
+            L.solve_sap(eta, block, r=1e-10, nkv=8)
+        assert e.value.code == -6
+        L.set_alpha(np.ones(dims[0]))
+        S, cpp, info = L.solve_sap(eta, block, r=1e-10, nkv=8)
+    assert info["status"] == 0
+    res = eta - oracle.apply(U, C, 0.2, S, bc_t=0)
+    assert np.linalg.norm(res) / np.linalg.norm(eta) <= 1.0001e-10
