@@ -194,9 +194,9 @@ def test_solve_sap_dev_matches_host():
 
 def test_sap_nonfinite_reports_and_recovers():
     """A time profile whose hop ratio (1e40) exceeds the FP32 range makes the
-    FP32 block solves non-finite: GCR's device-side guards keep the norm and
-    coefficient steps from acting on it, the solve ends with
-    DP_ERR_NONFINITE, and the context solves normally afterwards."""
+    FP32 block solves non-finite: GCR stops at the first non-finite norm with
+    DP_ERR_NONFINITE, and the context solves normally afterwards (its vectors
+    are assigned afresh, not scaled by zero)."""
     import paper_1006_4028_amd as dp
     dims, block = (8, 4, 8, 4), (4, 2, 4, 2)
     log("test_sap_nonfinite_reports_and_recovers")
