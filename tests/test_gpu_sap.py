@@ -218,3 +218,27 @@ def test_sap_nonfinite_reports_and_recovers():
     assert info["status"] == 0
     res = eta - oracle.apply(U, C, 0.2, S, bc_t=0)
     assert np.linalg.norm(res) / np.linalg.norm(eta) <= 1.0001e-10
+
+
+def test_sap_max_iter_returns_partial_solution():
+    """Reaching max_iter reports DP_ERR_NOT_CONVERGED with the solution of the
+    completed restart cycles, whose residual the oracle confirms is below
+    the source's; the preconditioner entry point rejects a bad blocking."""
+    import paper_1006_4028_amd as dp
+    dims, block = (8, 4, 8, 4), (4, 2, 4, 2)
+    log("test_sap_max_iter_returns_partial_solution")
+    U = synth.gauge_su3(dims, 0.4, 54)
+    C = oracle.clover(U, 1.6)
+    eta = synth.point_sources_12(dims, (0, 0, 0, 0))[2]
+    with lattice(dims) as L:
+        L.set_gauge(U)
+        L.set_clover(1.6)
+        L.set_mass(0.05)
+        S, cpp, info = L.solve_sap(eta, block, r=1e-12, nkv=2, max_iter=4, allow_unconverged=True)
+        assert info["status"] == -4 and info["iters"] == 4
+        res = np.linalg.norm(eta - oracle.apply(U, C, 0.05, S)) / np.linalg.norm(eta)
+        log(f"  residual after 4 iterations {res:.2e} (GPU {info['true_res']:.2e})")
+        assert res < 0.1 and abs(res / info["true_res"] - 1) < 1e-6
+        with pytest.raises(dp.DPError) as e:
+            L.sap_precondition(eta, (3, 2, 4, 2))
+        assert e.value.code == -1
