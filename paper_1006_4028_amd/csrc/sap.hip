@@ -172,24 +172,23 @@ __global__ void __launch_bounds__(kBlock) vec_convert_kernel(Geom g, SpinorRef x
   SpinorIO<PO>::store(y, p, i, g.Vp, v);
 }
 
-// op 0: y += a x (a complex);  op 1: y = s y (s = a.x real);  op 2: y = x - y;
-// op 3: y = 0;  op 4: y = x  (3 and 4 do not read y, so that whatever a
-// failed solve left in it is overwritten, not carried: 0 * NaN is NaN)
+// op 0: y += a x (a complex);  op 1: y = x - y;  op 2: y = 0;  op 3: y = x
+// (2 and 3 do not read y, so that whatever a failed solve left in it is
+// overwritten, not carried: 0 * NaN is NaN)
 __global__ void __launch_bounds__(kBlock) vec_update_kernel(Geom g, int op, double ar, double ai, SpinorRef x,
                                                             SpinorRef y) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int p = blockIdx.y;
   if (i >= g.Vh) return;
   cx<double> vx[12], vy[12];
-  if (op <= 2) SpinorIO<F64>::load(y, p, i, g.Vp, vy);
-  if (op != 1 && op != 3) SpinorIO<F64>::load(x, p, i, g.Vp, vx);
+  if (op <= 1) SpinorIO<F64>::load(y, p, i, g.Vp, vy);
+  if (op != 2) SpinorIO<F64>::load(x, p, i, g.Vp, vx);
   const cx<double> a{ar, ai};
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
     if (op == 0) vy[c] = vy[c] + cmul(a, vx[c]);
-    else if (op == 1) vy[c] = ar * vy[c];
-    else if (op == 2) vy[c] = vx[c] - vy[c];
-    else if (op == 3) vy[c] = cx<double>{0.0, 0.0};
+    else if (op == 1) vy[c] = vx[c] - vy[c];
+    else if (op == 2) vy[c] = cx<double>{0.0, 0.0};
     else vy[c] = vx[c];
   }
   SpinorIO<F64>::store(y, p, i, g.Vp, vy);
@@ -1270,8 +1269,8 @@ int sap_solve(dp_ctx* c, const Blocking& b, const double2* eta_dev, const dp_sap
   DP_TRY(vec_dot(c, s, s.eta, s.eta, &e2));
   const double target = p->r * std::sqrt(e2.real());
   // x = 0, r = eta'
-  DP_TRY(vec_update(c, 3, zc(0.0, 0.0), s.x, s.x));
-  DP_TRY(vec_update(c, 4, zc(0.0, 0.0), s.eta, s.r));
+  DP_TRY(vec_update(c, 2, zc(0.0, 0.0), s.x, s.x));
+  DP_TRY(vec_update(c, 3, zc(0.0, 0.0), s.eta, s.r));
   int iters = 0, status = DP_ERR_NOT_CONVERGED, outer = 0;
   double rn = std::sqrt(e2.real());
   if (!std::isfinite(rn)) status = DP_ERR_NONFINITE;
@@ -1335,7 +1334,7 @@ int sap_solve(dp_ctx* c, const Blocking& b, const double2* eta_dev, const dp_sap
     for (int j = 0; j < k; ++j) DP_TRY(vec_update(c, 0, al[j], s.z[j], s.x));
     // true residual r = eta' - D' x
     DP_TRY(apply_full(c, s, F64, s.x, s.r));
-    DP_TRY(vec_update(c, 2, zc(0.0, 0.0), s.eta, s.r));
+    DP_TRY(vec_update(c, 1, zc(0.0, 0.0), s.eta, s.r));
     zc r2;
     DP_TRY(vec_dot(c, s, s.r, s.r, &r2));
     rn = std::sqrt(r2.real());
