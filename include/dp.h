@@ -280,9 +280,11 @@ int dp_solve_sap_dev(dp_ctx* ctx, const void* eta_dev, const dp_sap_params* p, v
  * already in the preconditioned variables (no beta is applied).  Uses
  * p->block, ncy, nmr and precision (validated as for dp_solve_sap); r, nkv
  * and max_iter are ignored.  With FP32 block solves on blocks of at most
- * 256 sites one kernel runs each colour pass (block solves in registers and
- * LDS); larger blocks and FP64 launch the operator per minimal-residual
- * step.  Returns DP_ERR_INVALID_ARG / DP_ERR_BAD_STATE as dp_solve_sap. */
+ * 1536 sites one kernel runs each colour pass (block solves in registers
+ * and LDS; up to 256 sites a thread per site, above that up to three sites
+ * per thread); larger blocks and FP64 launch the operator per
+ * minimal-residual step.  Returns DP_ERR_INVALID_ARG / DP_ERR_BAD_STATE as
+ * dp_solve_sap. */
 int dp_sap_precondition(dp_ctx* ctx, const double* r, const dp_sap_params* p, double* psi);
 
 /* Instrumentation (no passage of the paper: it reports no timings).
