@@ -76,7 +76,9 @@ def build(verbose=False, jobs=8):
     with open(RESOURCES, "w") as f:
         json.dump(res, f, indent=0, sort_keys=True)
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    # roctx: the library's named ranges for rocprofv3 --marker-trace
+    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-L/opt/rocm/lib",
+           "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

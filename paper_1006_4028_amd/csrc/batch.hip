@@ -395,6 +395,7 @@ int dp_batch_admit(dp_batch* b, int ncols, const void* eta_dev, void* S_dev, dou
 
 int dp_batch_step(dp_batch* b, int k, int* ndone) {
   if (!b || k <= 0) return DP_ERR_INVALID_ARG;
+  TraceRange tr("dp_batch_step");
   dp_ctx* c = b->c;
   DP_HIP(c, hipSetDevice(c->device));
   Workspace& w = b->w;
@@ -402,7 +403,10 @@ int dp_batch_step(dp_batch* b, int k, int* ndone) {
   bool any = false;
   for (int s = 0; s < n; ++s) any |= b->slots[s].in_inner;
   if (any) {
-    DP_TRY(inner_iterations(b, k));
+    {
+      TraceRange ti("inner_iterations");
+      DP_TRY(inner_iterations(b, k));
+    }
     SlotScalars* hsc = w.h_sc.as<SlotScalars>();
     int* hm = w.h_mask.as<int>() + (size_t)3 * w.nslots;
     DP_HIP(c, hipMemcpyAsync(hsc, w.sc.p, sizeof(SlotScalars) * n, hipMemcpyDeviceToHost, c->stream));
@@ -427,6 +431,7 @@ int dp_batch_step(dp_batch* b, int k, int* ndone) {
     }
     c->mask_count[w.mask_inner.p] = (int)std::count(b->m_inner.begin(), b->m_inner.end(), 1);
     if (any_pend) {
+      TraceRange to("outer_step");
       std::vector<int> fin;
       DP_TRY(outer_step(b, pend, fin));
       DP_TRY(finish(b, fin));
@@ -602,6 +607,7 @@ static int solve_batch(dp_ctx* c, const double2* eta, int n, const dp_params& P,
 }
 
 int dp_solve(dp_ctx* c, const double* eta, int nrhs, const dp_params* p, double* S, double* cpp, dp_info* info) {
+  TraceRange tr("dp_solve");
   if (!c || !eta) return fail(c, DP_ERR_INVALID_ARG, "null argument");
   DP_HIP(c, hipSetDevice(c->device));
   DP_TRY(validate_params(c, nrhs, p));
@@ -621,6 +627,7 @@ int dp_solve(dp_ctx* c, const double* eta, int nrhs, const dp_params* p, double*
 
 int dp_solve_dev(dp_ctx* c, const void* eta, int nrhs, const dp_params* p, void* S, double* cpp, dp_info* info,
                  void* stream) {
+  TraceRange tr("dp_solve_dev");
   if (!c || !eta) return fail(c, DP_ERR_INVALID_ARG, "null argument");
   DP_HIP(c, hipSetDevice(c->device));
   DP_TRY(validate_params(c, nrhs, p));

@@ -5,6 +5,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/dp.h"
 #include "dp_common.h"
 
@@ -232,6 +234,16 @@ int hip_fail(dp_ctx* c, hipError_t e, const char* expr, int line);
     int rc_ = (expr);             \
     if (rc_ != DP_OK) return rc_; \
   } while (0)
+
+// A named roctx range over a scope: the library's phases (solve, inner
+// iterations, outer step, SAP application) appear in rocprofv3
+// --marker-trace beside the kernels; without a tracer the calls do nothing.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 bool env_pad();
 double now_s();

@@ -1056,6 +1056,7 @@ int dp_apply_dev_noalloc(dp_ctx* c, const void* in, void* out, int nrhs, int fla
 }
 
 int dp_apply(dp_ctx* c, const double* in, double* out, int flags) {
+  TraceRange tr("dp_apply");
   if (!c || !in || !out) return fail(c, DP_ERR_INVALID_ARG, "null argument");
   DP_TRY(check_apply_flags(c, flags));
   DP_HIP(c, hipSetDevice(c->device));
@@ -1074,6 +1075,7 @@ int dp_apply(dp_ctx* c, const double* in, double* out, int flags) {
 }
 
 int dp_apply_dev(dp_ctx* c, const void* in, void* out, int nrhs, int flags, void* stream) {
+  TraceRange tr("dp_apply_dev");
   if (!c || !in || !out) return fail(c, DP_ERR_INVALID_ARG, "null argument");
   if (nrhs <= 0) return fail(c, DP_ERR_INVALID_ARG, "nrhs must be positive");
   DP_TRY(check_apply_flags(c, flags));

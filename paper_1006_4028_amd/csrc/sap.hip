@@ -1158,6 +1158,7 @@ int sap_apply_fused(dp_ctx* c, SapState& s, const Blocking& b, int ncy, int nmr)
 
 // z = M r (r, z FP64)
 int precondition(dp_ctx* c, SapState& s, const Blocking& b, int ncy, int nmr, const Field& r, const Field& z) {
+  TraceRange tr("sap_precondition");
   if (s.fused) {
     hipLaunchKernelGGL(sap_to_block_kernel, site_grid(c->g), dim3(kBlock), 0, c->stream, c->g, b, r.ref(),
                        s.rbl.as<float4>());
@@ -1385,6 +1386,7 @@ int sap_check(dp_ctx* c, const dp_sap_params* p) {
 extern "C" int dp_solve_sap(dp_ctx* c, const double* eta, const dp_sap_params* p, double* S, double* cpp,
                             dp_info* info) {
   if (!c || !eta || !p) return DP_ERR_INVALID_ARG;
+  TraceRange tr("dp_solve_sap");
   DP_TRY(sap_check(c, p));
   Blocking b;
   DP_TRY(sap_prepare(c, p, p->nkv, &b));
@@ -1401,6 +1403,7 @@ extern "C" int dp_solve_sap(dp_ctx* c, const double* eta, const dp_sap_params* p
 extern "C" int dp_solve_sap_dev(dp_ctx* c, const void* eta_dev, const dp_sap_params* p, void* S_dev, double* cpp,
                                 dp_info* info, void* hip_stream) {
   if (!c || !eta_dev || !p) return DP_ERR_INVALID_ARG;
+  TraceRange tr("dp_solve_sap_dev");
   DP_TRY(sap_check(c, p));
   const size_t bytes = (size_t)2 * c->g.Vh * 12 * sizeof(double2);
   const char* e0 = static_cast<const char*>(eta_dev);
